@@ -1,0 +1,333 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these compare the oracle with itself: each check is a closed form, a
+textbook routine written separately, a library routine, or an invariant of
+the method (section 2, Table 1, eqs. 1.2-1.3, section 2.2).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as sla
+
+import workloads as W
+from oracle import blk_oracle as O
+from tests import pins
+
+VARIANTS = ["cocg", "cocr", "cocg_rq", "cocr_rq"]
+
+
+# ---------------------------------------------------------------------------
+# Generators (the synthetic operators stand in for the paper's matrices)
+# ---------------------------------------------------------------------------
+
+def test_helmholtz_complex_symmetric_not_hermitian():
+    for A in (W.helmholtz2d(7, 5.0, 0.05), W.helmholtz3d(5, 3.0, 0.02)):
+        D = A.todense()
+        assert np.array_equal(D, D.T)
+        assert not np.allclose(D, D.conj().T)
+
+
+def test_helmholtz_nnz_and_entries():
+    A, B = W.config1()
+    assert A.n == 4096 and A.nnz == 5 * 64 * 64 - 4 * 64 == 20224
+    assert B.shape == (4096, 4) and B.dtype == np.complex128
+    h = 1.0 / 65
+    assert A.val[0] == pytest.approx(4 / h**2 - 400 * (1 + 0.05j))
+    assert A.val[0] == pytest.approx(16500 - 20j)
+    for N in (4, 9):
+        A3 = W.config2_operator(N)
+        assert A3.nnz == 7 * N**3 - 6 * N**2
+        assert np.all(np.diff(A3.rowptr) >= 4)
+        for r in range(A3.n):  # sorted columns
+            c = A3.colind[A3.rowptr[r]:A3.rowptr[r + 1]]
+            assert np.all(np.diff(c) > 0)
+
+
+@pytest.mark.parametrize("a,b", [(1, 1), (2, 3), (5, 1)])
+def test_helmholtz2d_sine_mode_eigenpair(a, b):
+    N, k, delta = 12, 4.0, 0.05
+    h = 1.0 / (N + 1)
+    D = W.helmholtz2d(N, k, delta).todense()
+    x, y = W.grid_coords2d(N)
+    v = np.sin(a * math.pi * x) * np.sin(b * math.pi * y)
+    lam = (4 / h**2) * (math.sin(a * math.pi * h / 2) ** 2 + math.sin(b * math.pi * h / 2) ** 2) - k * k * (1 + 1j * delta)
+    assert pins.rel(D @ v, lam * v) < 1e-12
+
+
+def test_helmholtz3d_sine_mode_eigenpair():
+    N, kh, delta = 6, 0.25, 0.02
+    h = 1.0 / (N + 1)
+    k = kh / h
+    D = W.helmholtz3d(N, k, delta).todense()
+    idx = np.arange(N**3)
+    x, y, z = (idx % N + 1) * h, (idx // N % N + 1) * h, (idx // N**2 + 1) * h
+    a, b, c = 2, 1, 3
+    v = np.sin(a * math.pi * x) * np.sin(b * math.pi * y) * np.sin(c * math.pi * z)
+    lam = (4 / h**2) * sum(math.sin(q * math.pi * h / 2) ** 2 for q in (a, b, c)) - k * k * (1 + 1j * delta)
+    assert pins.rel(D @ v, lam * v) < 1e-12
+
+
+def test_greens_sphere_entries():
+    n, k = 64, 2 * math.pi * 2
+    A = W.greens_sphere(n, k, row_block=16)
+    assert np.array_equal(A, A.T)
+    assert np.all(np.diag(A) == 1 + 0.5j)
+    pts = W.fibonacci_sphere(n)
+    assert np.allclose(np.sum(pts**2, axis=1), 1.0)
+    i, j = 3, 41
+    r = math.dist(pts[i], pts[j])
+    assert A[i, j] == pytest.approx(complex(math.cos(k * r), math.sin(k * r)) / (4 * math.pi * r), rel=1e-14)
+
+
+def test_cgauss_seeded():
+    a = W.cgauss(100, 3, seed=7)
+    b = W.cgauss(100, 3, seed=7)
+    assert np.array_equal(a, b) and a.flags.c_contiguous
+    assert abs(np.mean(np.abs(W.cgauss(20000, 2, 1)) ** 2) - 1.0) < 0.03
+
+
+# ---------------------------------------------------------------------------
+# Primitives
+# ---------------------------------------------------------------------------
+
+def test_thin_qr_positive_diagonal():
+    rng = np.random.default_rng(0)
+    Wb = rng.standard_normal((50, 6)) + 1j * rng.standard_normal((50, 6))
+    Q, R = O.thin_qr_pos(Wb)
+    assert np.allclose(Q.conj().T @ Q, np.eye(6), atol=1e-14)
+    assert np.allclose(np.tril(R, -1), 0)
+    assert np.all(np.abs(np.diag(R).imag) < 1e-14) and np.all(np.diag(R).real > 0)
+    assert pins.rel(Q @ R, Wb) < 1e-14
+    # uniqueness: the R factor of a full-rank block equals the Cholesky factor of W^H W
+    L = np.linalg.cholesky(Wb.conj().T @ Wb)
+    assert pins.rel(R, L.conj().T) < 1e-12
+
+
+def test_thin_qr_rank_deficient_raises():
+    rng = np.random.default_rng(1)
+    Wb = rng.standard_normal((30, 3)) + 0j
+    Wb[:, 2] = Wb[:, 0]
+    with pytest.raises(O.Breakdown):
+        O.thin_qr_pos(Wb)
+
+
+def test_gram_is_unconjugated_and_spmm_matches_dense():
+    A, B = W.config1()
+    Aop = O.as_operator(A)
+    assert pins.rel(O.apply(Aop, B), A.todense() @ B) < 1e-14
+    G = O.gram_t(B, B)
+    assert np.allclose(G, G.T)  # unconjugated self-form is symmetric, not Hermitian
+    assert not np.allclose(G, G.conj().T)
+
+
+# ---------------------------------------------------------------------------
+# Method pins
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("method", VARIANTS)
+@pytest.mark.parametrize("n,p,seed", [(48, 1, 0), (60, 3, 1), (64, 4, 2)])
+def test_iterates_equal_petrov_galerkin_closed_form(method, n, p, seed):
+    """Table 1 + eq. (1.3): X_m is the unique Petrov-Galerkin iterate."""
+    A = pins.well_conditioned_cs(n, seed)
+    rng = np.random.default_rng(100 + seed)
+    B = rng.standard_normal((n, p)) + 1j * rng.standard_normal((n, p))
+    X0 = 0.1 * (rng.standard_normal((n, p)) + 1j * rng.standard_normal((n, p)))
+    m_max = 6
+    r = O.solve_block(method, A, B, X0=X0, tol=1e-30, maxit=m_max, record=True)
+    assert r.status == O.MAXIT and r.iters == m_max
+    for m in range(m_max + 1):
+        ref = pins.petrov_galerkin_iterate(A, B, X0, m, method)
+        assert pins.rel(r.Xs[m], ref) < 1e-11, (method, m)
+
+
+@pytest.mark.parametrize("method,scalar", [("cocg", pins.scalar_cocg), ("cocg_rq", pins.scalar_cocg),
+                                           ("cocr", pins.scalar_cocr), ("cocr_rq", pins.scalar_cocr)])
+def test_p1_reduces_to_scalar_method(method, scalar):
+    A = W.helmholtz2d(8, 3.0, 0.05).todense()
+    b = W.cgauss(A.shape[0], 1, seed=3)
+    r = O.solve_block(method, A, b, tol=1e-30, maxit=20, record=True)
+    xs = scalar(A, b[:, 0], 20)
+    for m in range(21):
+        assert pins.rel(r.Xs[m][:, 0], xs[m]) < 1e-12, m
+
+
+def _spd(n, seed):
+    rng = np.random.default_rng(seed)
+    G = rng.standard_normal((n, n))
+    return G @ G.T / n + np.eye(n)
+
+
+@pytest.mark.parametrize("method", ["cocg", "cocg_rq"])
+def test_real_spd_cocg_is_cg(method):
+    n = 60
+    A = _spd(n, 4)
+    b = np.random.default_rng(5).standard_normal(n)
+    xs = []
+    sla.cg(A, b, rtol=1e-300, maxiter=10, callback=lambda xk: xs.append(xk.copy()))
+    r = O.solve_block(method, A, b[:, None].astype(complex), tol=1e-30, maxit=10, record=True)
+    for m in range(1, 11):
+        assert np.max(np.abs(r.Xs[m][:, 0].imag)) < 1e-14
+        assert pins.rel(r.Xs[m][:, 0].real, xs[m - 1]) < 1e-10, m
+
+
+@pytest.mark.parametrize("method", ["cocr", "cocr_rq"])
+def test_real_spd_cocr_is_minres(method):
+    """On a real SPD matrix COCR is CR, whose iterates minimize ||b - A x||_2
+    over the Krylov space, as MINRES's do."""
+    n = 60
+    A = _spd(n, 6)
+    b = np.random.default_rng(7).standard_normal(n)
+    xs = []
+    sla.minres(A, b, rtol=1e-300, maxiter=8, callback=lambda xk: xs.append(xk.copy()))
+    r = O.solve_block(method, A, b[:, None].astype(complex), tol=1e-30, maxit=8, record=True)
+    for m in range(1, 9):
+        assert pins.rel(r.Xs[m][:, 0].real, xs[m - 1]) < 1e-9, m
+
+
+@pytest.mark.parametrize("method", VARIANTS)
+@pytest.mark.parametrize("n,p", [(8, 1), (16, 2), (32, 4), (64, 8)])
+def test_tiny_matches_dense_solve(method, n, p):
+    A = pins.well_conditioned_cs(n, n + p)
+    B = W.cgauss(n, p, seed=n)
+    r = O.solve_block(method, A, B, tol=1e-12, maxit=4 * n)
+    assert r.status == O.CONVERGED
+    Xs = np.linalg.solve(A, B)
+    kappa = np.linalg.cond(A)
+    assert pins.rel(r.X, Xs) <= 10 * kappa * 1e-12
+    assert O.true_relres(A, B, r.X) < 1e-11
+
+
+@pytest.mark.parametrize("method", VARIANTS)
+@pytest.mark.parametrize("n,p", [(24, 3), (40, 8), (36, 4)])
+def test_finite_termination(method, n, p):
+    """The block Krylov space grows by p per step, so ceil(n/p) steps suffice."""
+    A = pins.well_conditioned_cs(n, 11)
+    B = W.cgauss(n, p, seed=12)
+    r = O.solve_block(method, A, B, tol=1e-10, maxit=n)
+    assert r.status == O.CONVERGED
+    assert r.iters <= math.ceil(n / p), r.iters
+
+
+@pytest.mark.parametrize("base", ["cocg", "cocr"])
+def test_rq_same_iterates_as_plain(base):
+    A, B = W.config1()
+    a = O.solve_block(base, A, B, tol=1e-30, maxit=5, record=True)
+    b = O.solve_block(base + "_rq", A, B, tol=1e-30, maxit=5, record=True)
+    for m in range(6):
+        assert pins.rel(b.Xs[m], a.Xs[m]) < 1e-10 if m else True
+        assert abs(a.hist[m] - b.hist[m]) <= 1e-10 * a.hist[m]
+
+
+@pytest.mark.parametrize("method", ["cocg_rq", "cocr_rq"])
+def test_xi_norm_is_true_residual(method):
+    """Section 2.2: ||R_m||_F = ||xi_m||_F."""
+    A, B = W.config1()
+    r = O.solve_block(method, A, B, tol=1e-30, maxit=30, record=True)
+    Aop = O.as_operator(A)
+    for m in range(0, 31, 5):
+        true = O.fro(B - O.apply(Aop, r.Xs[m])) / O.fro(B)
+        assert abs(r.hist[m] - true) <= 1e-10 * true, m
+
+
+@pytest.mark.parametrize("method", VARIANTS)
+def test_right_multiplication_equivariance(method):
+    """The block space of eq. (1.3) is closed under right multiplication by
+    invertible G, so X(BG) = X(B) G; for unitary G the history is unchanged."""
+    n, p = 50, 3
+    A = pins.well_conditioned_cs(n, 21)
+    B = W.cgauss(n, p, seed=22)
+    rng = np.random.default_rng(23)
+    G = rng.standard_normal((p, p)) + 1j * rng.standard_normal((p, p)) + 2 * np.eye(p)
+    U, _ = np.linalg.qr(rng.standard_normal((p, p)) + 1j * rng.standard_normal((p, p)))
+    a = O.solve_block(method, A, B, tol=1e-30, maxit=5, record=True)
+    b = O.solve_block(method, A, B @ G, tol=1e-30, maxit=5, record=True)
+    c = O.solve_block(method, A, B @ U, tol=1e-30, maxit=5)
+    for m in range(6):
+        assert pins.rel(b.Xs[m], a.Xs[m] @ G) < 1e-11
+    assert np.allclose(a.hist, c.hist, rtol=1e-11)
+
+
+@pytest.mark.parametrize("method", ["cocg", "cocg_rq", "cocr", "cocr_rq"])
+def test_table1_orthogonality(method):
+    """COCG: R_i^T R_j = 0 and P_i^T A P_j = 0 (i != j).
+    COCR: R_i^T A R_j = 0 and (A P_i)^T (A P_j) = 0."""
+    n, p = 80, 2
+    A = pins.well_conditioned_cs(n, 31)
+    B = W.cgauss(n, p, seed=32)
+    r = O.solve_block(method, A, B, tol=1e-30, maxit=12, record=True)
+    Rs, Ps = r.Rs, r.Ps
+    for i in range(len(Rs)):
+        for j in range(i + 1, len(Rs)):
+            if method.startswith("cocg"):
+                f1, f2 = Rs[i].T @ Rs[j], Ps[i].T @ A @ Ps[j]
+                s1 = np.linalg.norm(Rs[i]) * np.linalg.norm(Rs[j])
+                s2 = np.linalg.norm(Ps[i]) * np.linalg.norm(A @ Ps[j])
+            else:
+                f1, f2 = Rs[i].T @ A @ Rs[j], (A @ Ps[i]).T @ (A @ Ps[j])
+                s1 = np.linalg.norm(Rs[i]) * np.linalg.norm(A @ Rs[j])
+                s2 = np.linalg.norm(A @ Ps[i]) * np.linalg.norm(A @ Ps[j])
+            assert np.linalg.norm(f1) <= 1e-9 * s1, (i, j)
+            assert np.linalg.norm(f2) <= 1e-9 * s2, (i, j)
+
+
+def test_printed_alpha_rhs_equal_early_then_unstable():
+    """Algorithm 3 prints Q^T U for the alpha' right-hand side; Q^T V is what
+    Algorithm 1 gives.  Equal in exact arithmetic (early iterates agree), but
+    the printed form diverges on the 2D Helmholtz workload."""
+    A, B = W.config1()
+    a = O.bl_cocr_rq(A, B, tol=1e-8, maxit=2000)
+    b = O.bl_cocr_rq(A, B, tol=1e-8, maxit=2000, alpha_rhs="QtU")
+    assert np.allclose(a.hist[:10], b.hist[:10], rtol=1e-12)
+    assert a.status == O.CONVERGED
+    assert b.status != O.CONVERGED or b.iters > a.iters
+
+
+# ---------------------------------------------------------------------------
+# Stopping, edge cases and status
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("method", VARIANTS)
+def test_config1_converges(method):
+    A, B = W.config1()
+    r = O.solve_block(method, A, B, tol=1e-8, maxit=2000)
+    assert r.status == O.CONVERGED
+    assert len(r.hist) == r.iters + 1
+    assert r.hist[-1] <= 1e-8 < min(r.hist[:-1])
+    assert O.true_relres(A, B, r.X) < 3e-8
+
+
+@pytest.mark.parametrize("method", VARIANTS)
+def test_zero_rhs(method):
+    A = pins.well_conditioned_cs(10, 0)
+    r = O.solve_block(method, A, np.zeros((10, 2), complex))
+    assert r.status == O.CONVERGED and r.iters == 0 and np.all(r.X == 0)
+
+
+@pytest.mark.parametrize("method", VARIANTS)
+def test_maxit(method):
+    A, B = W.config1()
+    r = O.solve_block(method, A, B, tol=1e-8, maxit=3)
+    assert r.status == O.MAXIT and r.iters == 3 and len(r.hist) == 4
+
+
+@pytest.mark.parametrize("method", VARIANTS)
+def test_duplicate_columns_break_down(method):
+    A = pins.well_conditioned_cs(30, 3)
+    B = W.cgauss(30, 3, seed=4)
+    B[:, 2] = B[:, 0]
+    r = O.solve_block(method, A, B, tol=1e-10, maxit=50)
+    assert r.status == O.BREAKDOWN and r.iters == 0
+    assert np.all(r.X == 0)
+
+
+@pytest.mark.parametrize("method", VARIANTS)
+def test_x0_is_respected(method):
+    n, p = 40, 2
+    A = pins.well_conditioned_cs(n, 8)
+    B = W.cgauss(n, p, seed=9)
+    Xs = np.linalg.solve(A, B)
+    r = O.solve_block(method, A, B, X0=Xs, tol=1e-10, maxit=10)
+    assert r.iters == 0 and r.status == O.CONVERGED and np.array_equal(r.X, Xs)
