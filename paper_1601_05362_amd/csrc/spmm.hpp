@@ -1,0 +1,149 @@
+// Operator application Y = A Z for a complex symmetric CSR matrix and an
+// n x p block with interleaved complex columns (the one block product per
+// iteration of section 2.1).
+//
+// Each row of A is read once for all p columns: the PP lanes that own a row
+// (one lane per column) walk the row's nonzeros together, every lane reading
+// the same (colind, val) entry and its own column of the neighbour row of Z.
+// Accumulation is in the storage precision (FP64 for complex128, FP32 for
+// complex64).  Optional fused epilogues: Y = C - A Z (initial / true residual), the
+// unconjugated Gram Z^T Y (the Z row of Y's own index is the diagonal
+// neighbour), and ||Y||_F^2.
+#pragma once
+
+#include "common.hpp"
+#include "rowpass.hpp"
+
+namespace blk {
+
+template <typename T, int PP, bool SUB, bool STORE, bool GRAM, bool NORM>
+__global__ __launch_bounds__(NT) void k_spmm(int64_t n, const int32_t* __restrict__ rowptr,
+                                             const int32_t* __restrict__ colind,
+                                             const cx<T>* __restrict__ val,
+                                             const cx<T>* __restrict__ Z, int ldz,
+                                             const cx<T>* __restrict__ Cm, int ldc,
+                                             cx<T>* __restrict__ Y, int ldy, int p, double* part,
+                                             int E, const DevState* st, int gate) {
+  if (st && gate >= st->stop_iter) return;
+  constexpr int RPB = NT / PP;
+  __shared__ cx<T> zs[GRAM ? NT : 1];
+  __shared__ cx<T> ys[GRAM ? NT : 1];
+  __shared__ double sh[NT / 64];
+  GramAcc<T, double, PP, false> g;
+  if (GRAM) g.zero();
+  double nrm = 0.0;
+  const int lr = threadIdx.x / PP, c = threadIdx.x % PP;
+  const bool cok = c < p;
+  int64_t t0, t1;
+  tile_range((n + RPB - 1) / RPB, t0, t1);
+  for (int64_t t = t0; t < t1; ++t) {
+    const int64_t row = t * RPB + lr;
+    cx<T> y = czero<T>();
+    cx<T> zr = czero<T>();
+    if (row < n) {
+      const int k0 = rowptr[row], k1 = rowptr[row + 1];
+      cx<T> acc = czero<T>();
+      for (int k = k0; k < k1; ++k) {
+        const int64_t j = colind[k];
+        const cx<T> a = val[k];
+        const cx<T> z = cok ? Z[j * ldz + c] : czero<T>();
+        cfma(acc, a, z);
+      }
+      if (SUB) {
+        y = cok ? Cm[row * ldc + c] : czero<T>();
+        y = csub(y, acc);
+      } else {
+        y = acc;
+      }
+      if (!cok) y = czero<T>();
+      if (STORE && cok) Y[row * ldy + c] = y;
+      if (GRAM && cok) zr = Z[row * ldz + c];
+    }
+    if (NORM) nrm += (double)cabs2(y);
+    if (GRAM) {
+      __syncthreads();
+      zs[threadIdx.x] = zr;
+      ys[threadIdx.x] = y;
+      __syncthreads();
+      g.add(zs, ys);
+    }
+  }
+  if (GRAM || NORM) {
+    double* dst = part + (size_t)blockIdx.x * E;
+    if (GRAM) g.store(dst, p);
+    if (NORM) {
+      const double s = block_sum(nrm, sh);
+      if (threadIdx.x == 0) dst[E - 1] = s;
+    }
+  }
+}
+
+// Dense operator: Y = A Z (or C - A Z) with A row-major n x n (leading
+// dimension lda).  A tile of RPB rows x 32 columns of A is staged in LDS so
+// each row of A is read once, coalesced, for all p columns.
+template <typename T, int PP, bool SUB, bool STORE, bool GRAM, bool NORM>
+__global__ __launch_bounds__(NT) void k_dense(int64_t n, const cx<T>* __restrict__ Am, int64_t lda,
+                                              const cx<T>* __restrict__ Z, int ldz,
+                                              const cx<T>* __restrict__ Cm, int ldc,
+                                              cx<T>* __restrict__ Y, int ldy, int p, double* part,
+                                              int E, const DevState* st, int gate) {
+  if (st && gate >= st->stop_iter) return;
+  constexpr int RPB = NT / PP;
+  constexpr int KC = 32;  // columns of A per stage
+  __shared__ cx<T> as[RPB * KC];
+  __shared__ cx<T> zt[KC * PP];
+  __shared__ cx<T> zs[GRAM ? NT : 1];
+  __shared__ cx<T> ys[GRAM ? NT : 1];
+  __shared__ double sh[NT / 64];
+  GramAcc<T, double, PP, false> g;
+  if (GRAM) g.zero();
+  double nrm = 0.0;
+  const int lr = threadIdx.x / PP, c = threadIdx.x % PP;
+  const bool cok = c < p;
+  int64_t t0, t1;
+  tile_range((n + RPB - 1) / RPB, t0, t1);
+  for (int64_t t = t0; t < t1; ++t) {
+    const int64_t row = t * RPB + lr;
+    cx<T> acc = czero<T>();
+    for (int64_t k0 = 0; k0 < n; k0 += KC) {
+      __syncthreads();
+      for (int e = threadIdx.x; e < RPB * KC; e += NT) {
+        const int rr = e / KC, kk = e % KC;
+        const int64_t gr = t * RPB + rr, gk = k0 + kk;
+        as[e] = (gr < n && gk < n) ? Am[gr * lda + gk] : czero<T>();
+      }
+      for (int e = threadIdx.x; e < KC * PP; e += NT) {
+        const int kk = e / PP, cc = e % PP;
+        const int64_t gk = k0 + kk;
+        zt[e] = (gk < n && cc < p) ? Z[gk * ldz + cc] : czero<T>();
+      }
+      __syncthreads();
+#pragma unroll 8
+      for (int kk = 0; kk < KC; ++kk) cfma(acc, as[lr * KC + kk], zt[kk * PP + c]);
+    }
+    cx<T> y = czero<T>(), zr = czero<T>();
+    if (row < n && cok) {
+      y = SUB ? csub(Cm[row * ldc + c], acc) : acc;
+      if (STORE) Y[row * ldy + c] = y;
+      if (GRAM) zr = Z[row * ldz + c];
+    }
+    if (NORM) nrm += (double)cabs2(y);
+    if (GRAM) {
+      __syncthreads();
+      zs[threadIdx.x] = zr;
+      ys[threadIdx.x] = y;
+      __syncthreads();
+      g.add(zs, ys);
+    }
+  }
+  if (GRAM || NORM) {
+    double* dst = part + (size_t)blockIdx.x * E;
+    if (GRAM) g.store(dst, p);
+    if (NORM) {
+      const double s = block_sum(nrm, sh);
+      if (threadIdx.x == 0) dst[E - 1] = s;
+    }
+  }
+}
+
+}  // namespace blk

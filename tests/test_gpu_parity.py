@@ -1,0 +1,341 @@
+"""GPU path vs the CPU oracle, element by element, through the C ABI.
+
+Tolerances: FP64 kernels match the oracle's primitives to a few ulps of the
+operands' scale (1e-13 relative).  FP64 solves of the 2D Helmholtz workload
+with residual orthonormalization match the residual history to 1e-9 relative
+over the first 50 iterations, the final X to 1e-7 relative Frobenius and the
+iteration count within 2%.  Where rounding alone moves the oracle further
+(the plain variants, whose late convergence is chaotic, and operators with
+near-singular unconjugated p x p forms), the bounds are the oracle's own
+spread under a 1e-15 perturbation of B, measured in the test.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import blk_oracle as O
+from tests import pins
+
+pytestmark = pytest.mark.gpu
+
+VARIANTS = [("cocg", False), ("cocr", False), ("cocg", True), ("cocr", True)]
+ORACLE_NAME = {("cocg", False): "cocg", ("cocr", False): "cocr", ("cocg", True): "cocg_rq",
+               ("cocr", True): "cocr_rq"}
+
+
+@pytest.fixture(scope="module")
+def pkg():
+    import paper_1601_05362_amd as p
+
+    p._capi.load()
+    return p
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def cfg1(pkg, dev):
+    A, B = W.config1()
+    return A, B, pkg.CsrOperator.from_arrays(A.rowptr, A.colind, A.val, device=dev), torch.as_tensor(B, device=dev)
+
+
+def _solve(pkg, method, rq, Ad, Bd, **kw):
+    fn = pkg.blk_cocg_solve if method == "cocg" else pkg.blk_cocr_solve
+    return fn(Ad, Bd, rq=rq, **kw)
+
+
+def _relerr(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+# ---------------------------------------------------------------------------
+# Kernels
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("p", [1, 3, 4, 8, 13, 16, 32])
+def test_spmm_matches_oracle(pkg, dev, cfg1, p):
+    A, _, Ad, _ = cfg1
+    Z = W.cgauss(A.n, p, seed=p)
+    C = W.cgauss(A.n, p, seed=100 + p)
+    Zd, Cd = torch.as_tensor(Z, device=dev), torch.as_tensor(C, device=dev)
+    Aop = O.as_operator(A)
+    Y_ref = O.apply(Aop, Z)
+    Y, G = pkg.blk_spmm_z(Ad, Zd, gram=True)
+    scale = np.abs(A.val).max() * np.abs(Z).max()
+    assert np.max(np.abs(Y.cpu().numpy() - Y_ref)) <= 1e-13 * scale * 7
+    G_ref = O.gram_t(Z, Y_ref)
+    assert _relerr(G, G_ref) < 1e-12
+    Y2 = pkg.blk_spmm_z(Ad, Zd, C_=Cd)
+    assert np.max(np.abs(Y2.cpu().numpy() - (C - Y_ref))) <= 1e-13 * scale * 7
+
+
+def test_spmm_ragged_rows_and_ld(pkg, dev):
+    """n not a multiple of any tile, empty rows, unsorted columns, ld > p."""
+    rng = np.random.default_rng(5)
+    n, p = 1237, 5
+    D = np.zeros((n, n), complex)
+    for i in range(n):
+        if i % 97 == 13:
+            continue  # empty row
+        cols = rng.choice(n, size=rng.integers(1, 9), replace=False)
+        D[i, cols] = rng.standard_normal(len(cols)) + 1j * rng.standard_normal(len(cols))
+    rows, cols = np.nonzero(D)
+    order = rng.permutation(len(rows))  # unsorted within rows after stable sort by row
+    order = order[np.argsort(rows[order], kind="stable")]
+    rowptr = np.zeros(n + 1, np.int32)
+    np.add.at(rowptr, rows + 1, 1)
+    rowptr = np.cumsum(rowptr).astype(np.int32)
+    Ad = pkg.CsrOperator.from_arrays(rowptr, cols[order], D[rows[order], cols[order]], device=dev)
+    Zbig = torch.as_tensor(W.cgauss(n, 8, seed=6), device=dev)
+    Z = Zbig[:, :p]  # ld = 8
+    Y = pkg.blk_spmm_z(Ad, Z)
+    torch.cuda.synchronize()
+    ref = D @ Zbig[:, :p].cpu().numpy()
+    assert _relerr(Y.cpu().numpy(), ref) < 1e-14
+
+
+@pytest.mark.parametrize("p", [1, 4, 32])
+def test_spmm_c64_matches_oracle(pkg, dev, cfg1, p):
+    A, _, Ad, _ = cfg1
+    Z = W.cgauss(A.n, p, seed=7).astype(np.complex64)
+    Y = pkg.blk_spmm_c(Ad, torch.as_tensor(Z, device=dev)).cpu().numpy()
+    ref = O.apply(O.as_operator(A), Z.astype(np.complex128))
+    # FP32 storage of A and Z plus FP32 accumulation: a few ulps of |A||Z|
+    scale = np.abs(A.val).max() * np.abs(Z).max()
+    assert np.max(np.abs(Y - ref)) <= 5 * 6e-8 * scale * 5
+
+
+@pytest.mark.parametrize("p", [1, 2, 7, 16, 32])
+@pytest.mark.parametrize("conj", [False, True])
+def test_gram_matches_oracle(pkg, dev, p, conj):
+    n = 100003
+    Y = W.cgauss(n, p, seed=1)
+    Z = W.cgauss(n, p, seed=2)
+    G = pkg.blk_gram_z(torch.as_tensor(Y, device=dev), torch.as_tensor(Z, device=dev), conj=conj)
+    ref = (Y.conj().T if conj else Y.T) @ Z
+    assert _relerr(G, ref) < 1e-13
+
+
+@pytest.mark.parametrize("n,p", [(4096, 4), (50001, 32), (777, 9)])
+def test_thin_qr_matches_oracle(pkg, dev, n, p):
+    Wb = W.cgauss(n, p, seed=n) @ (np.eye(p) + 0.3 * W.cgauss(p, p, seed=1))
+    Q, R = pkg.blk_thin_qr_z(torch.as_tensor(Wb, device=dev))
+    Q = Q.cpu().numpy()
+    Qr, Rr = O.thin_qr_pos(Wb)
+    assert _relerr(R, Rr) < 1e-12
+    assert _relerr(Q, Qr) < 1e-12
+    assert np.max(np.abs(Q.conj().T @ Q - np.eye(p))) < 1e-13
+
+
+def test_thin_qr_rank_deficient(pkg, dev):
+    Wb = W.cgauss(1000, 3, seed=3)
+    Wb[:, 2] = Wb[:, 0]
+    with pytest.raises(ArithmeticError):
+        pkg.blk_thin_qr_z(torch.as_tensor(Wb, device=dev))
+
+
+# ---------------------------------------------------------------------------
+# Solvers
+# ---------------------------------------------------------------------------
+
+def _check_parity(r, ref, horizon=50, iters_tol=None, x_tol=1e-7):
+    """History to 1e-9 relative over the first `horizon` iterations, X to
+    x_tol relative Frobenius, iteration count within iters_tol (default 2%)."""
+    k = min(horizon + 1, len(ref.hist), len(r.hist))
+    h_gpu, h_ref = np.asarray(r.hist[:k]), np.asarray(ref.hist[:k])
+    herr = np.max(np.abs(h_gpu - h_ref) / h_ref)
+    xerr = _relerr(r.X.cpu().numpy(), ref.X)
+    assert herr < 1e-9, (herr, k)
+    assert xerr < x_tol, (xerr, x_tol)
+    if iters_tol is None:
+        iters_tol = max(1, math.floor(0.02 * ref.iters))
+    assert abs(r.iters - ref.iters) <= iters_tol, (r.iters, ref.iters, iters_tol)
+    assert r.status == ref.status
+
+
+def _oracle_with_spread(name, A, B, X0=None, tol=1e-8, maxit=1000, runs=4):
+    """The oracle's result plus how far rounding alone moves it: rerun on B
+    perturbed at 1e-15 relative.  Returns (ref, horizon, iters_tol, x_tol):
+    the history horizon over which the perturbed runs still agree to 1e-11
+    (capped at 50), and tolerances of twice the observed spread (at least 2%
+    of the count and 1e-7 in X)."""
+    ref = O.solve_block(name, A, B, X0=X0, tol=tol, maxit=maxit)
+    rng = np.random.default_rng(123)
+    horizon, it_spread, x_spread = 50, 0, 0.0
+    for _ in range(runs):
+        Bp = B * (1 + 1e-15 * rng.standard_normal(B.shape))
+        r = O.solve_block(name, A, Bp, X0=X0, tol=tol, maxit=maxit)
+        k = min(51, len(r.hist), len(ref.hist))
+        d = np.abs(np.array(r.hist[:k]) - np.array(ref.hist[:k])) / np.array(ref.hist[:k])
+        bad = np.nonzero(d > 1e-11)[0]
+        if len(bad):
+            horizon = min(horizon, int(bad[0]) - 1)
+        it_spread = max(it_spread, abs(r.iters - ref.iters))
+        x_spread = max(x_spread, _relerr(r.X, ref.X))
+    iters_tol = max(2, math.floor(0.02 * ref.iters), 2 * it_spread)
+    return ref, max(horizon, 1), iters_tol, max(1e-7, 2 * x_spread)
+
+
+@pytest.mark.parametrize("method,rq", VARIANTS)
+def test_config1_solver_parity(pkg, cfg1, method, rq):
+    A, B, Ad, Bd = cfg1
+    name = ORACLE_NAME[(method, rq)]
+    r = _solve(pkg, method, rq, Ad, Bd, tol=1e-8, maxit=2000)
+    if rq:
+        # the named parity configuration: 50 iterations, 2%, 1e-7
+        ref = O.solve_block(name, A, B, tol=1e-8, maxit=2000)
+        _check_parity(r, ref)
+        # the monitored norm is the true residual (section 2.2)
+        assert r.true_relres == pytest.approx(r.hist[-1], rel=1e-3)
+    else:
+        ref, H, it_tol, x_tol = _oracle_with_spread(name, A, B, tol=1e-8, maxit=2000)
+        _check_parity(r, ref, H, it_tol, x_tol)
+    assert r.true_relres < 3e-8
+
+
+@pytest.mark.parametrize("method,rq", VARIANTS)
+def test_solver_repeatable(pkg, cfg1, method, rq):
+    _, _, Ad, Bd = cfg1
+    a = _solve(pkg, method, rq, Ad, Bd, tol=1e-8, maxit=60)
+    b = _solve(pkg, method, rq, Ad, Bd, tol=1e-8, maxit=60)
+    assert np.array_equal(a.hist, b.hist)
+    assert torch.equal(a.X, b.X)
+
+
+@pytest.mark.parametrize("method,rq", VARIANTS)
+@pytest.mark.parametrize("p", [1, 3, 8])
+def test_small_dense_like_parity(pkg, dev, method, rq, p):
+    """Well-conditioned complex symmetric matrix stored as CSR, several p."""
+    n = 300
+    D = pins.well_conditioned_cs(n, 40 + p)
+    rows, cols = np.nonzero(np.ones((n, n)))
+    rowptr = np.arange(0, n * n + 1, n, dtype=np.int32)
+    Ad = pkg.CsrOperator.from_arrays(rowptr, cols, D.reshape(-1), device=dev)
+    B = W.cgauss(n, p, seed=p)
+    ref, H, it_tol, x_tol = _oracle_with_spread(ORACLE_NAME[(method, rq)], D, B, tol=1e-10, maxit=500)
+    r = _solve(pkg, method, rq, Ad, torch.as_tensor(B, device=dev), tol=1e-10, maxit=500)
+    _check_parity(r, ref, H, it_tol, x_tol)
+
+
+@pytest.mark.parametrize("method,rq", VARIANTS)
+def test_x0_and_in_place(pkg, dev, method, rq):
+    """A nonzero initial guess, with X aliasing X0 (in place)."""
+    n, p = 300, 3
+    D = pins.well_conditioned_cs(n, 77)
+    rowptr = np.arange(0, n * n + 1, n, dtype=np.int32)
+    cols = np.tile(np.arange(n), n)
+    Ad = pkg.CsrOperator.from_arrays(rowptr, cols, D.reshape(-1), device=dev)
+    B = W.cgauss(n, p, seed=78)
+    X0 = 0.3 * W.cgauss(n, p, seed=79)
+    name = ORACLE_NAME[(method, rq)]
+    ref, H, it_tol, x_tol = _oracle_with_spread(name, D, B, X0=X0, tol=1e-10, maxit=500)
+    X = torch.as_tensor(X0, device=dev).clone()
+    r = _solve(pkg, method, rq, Ad, torch.as_tensor(B, device=dev), X0=X, out=X, tol=1e-10, maxit=500)
+    assert r.X.data_ptr() == X.data_ptr()
+    _check_parity(r, ref, H, it_tol, x_tol)
+
+
+@pytest.mark.parametrize("method", ["cocg", "cocr"])
+def test_warm_start_config1(pkg, dev, cfg1, method):
+    """Config 1 restarted from the oracle's 40th iterate."""
+    A, B, Ad, Bd = cfg1
+    X0 = O.solve_block(method + "_rq", A, B, tol=1e-30, maxit=40).X
+    ref = O.solve_block(method + "_rq", A, B, X0=X0, tol=1e-8, maxit=2000)
+    r = _solve(pkg, method, True, Ad, Bd, X0=torch.as_tensor(X0, device=dev), tol=1e-8, maxit=2000)
+    _check_parity(r, ref, 50, max(2, math.floor(0.02 * ref.iters)))
+
+
+@pytest.mark.parametrize("method,rq", VARIANTS)
+def test_status_paths(pkg, dev, cfg1, method, rq):
+    A, B, Ad, Bd = cfg1
+    # maxit
+    r = _solve(pkg, method, rq, Ad, Bd, tol=1e-8, maxit=3)
+    assert r.status == pkg.BLK_MAXIT and r.iters == 3 and len(r.hist) == 4
+    ref = O.solve_block(ORACLE_NAME[(method, rq)], A, B, tol=1e-8, maxit=3)
+    assert np.allclose(r.hist, ref.hist, rtol=1e-12)
+    # zero right-hand side
+    r = _solve(pkg, method, rq, Ad, torch.zeros_like(Bd), tol=1e-8, maxit=10)
+    assert r.status == pkg.BLK_CONVERGED and r.iters == 0 and torch.count_nonzero(r.X) == 0
+    # maxit = 0
+    r = _solve(pkg, method, rq, Ad, Bd, tol=1e-8, maxit=0)
+    assert r.status == pkg.BLK_MAXIT and r.iters == 0
+    # duplicate columns: rank-deficient block
+    B2 = B.copy()
+    B2[:, 3] = B2[:, 1]
+    r = _solve(pkg, method, rq, Ad, torch.as_tensor(B2, device=dev), tol=1e-8, maxit=50)
+    ref = O.solve_block(ORACLE_NAME[(method, rq)], A, B2, tol=1e-8, maxit=50)
+    assert r.status == pkg.BLK_BREAKDOWN == ref.status
+    assert r.iters == ref.iters
+
+
+def test_einval(pkg, dev, cfg1):
+    A, B, Ad, Bd = cfg1
+    with pytest.raises(ValueError):
+        pkg.blk_cocr_solve(Ad, Bd, tol=0.0)
+    with pytest.raises(ValueError):
+        pkg.blk_cocr_solve(Ad, Bd, maxit=-1)
+    big = torch.zeros((A.n, 33), dtype=torch.complex128, device=dev)
+    with pytest.raises(ValueError):
+        pkg.blk_cocr_solve(Ad, big)
+    with pytest.raises(ValueError):
+        pkg.blk_cocr_solve(Ad, Bd, out=Bd)  # X aliases B
+
+
+# ---------------------------------------------------------------------------
+# Dense operator and mixed precision
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def greens_small(pkg, dev):
+    n, p = 1024, 4
+    k = 2 * math.pi * 1.5
+    A = W.greens_sphere(n, k)
+    B = W.plane_waves3d(W.fibonacci_sphere(n), k, p)
+    return A, B, pkg.DenseOperator(torch.as_tensor(A, device=dev)), torch.as_tensor(B, device=dev)
+
+
+def test_dense_apply_matches_oracle(pkg, greens_small):
+    A, B, Ad, Bd = greens_small
+    Y, G = pkg.blk_spmm_z(Ad, Bd, gram=True)
+    ref = A @ B
+    assert _relerr(Y.cpu().numpy(), ref) < 1e-13
+    assert _relerr(G, B.T @ ref) < 1e-12
+
+
+@pytest.mark.parametrize("method", ["cocg", "cocr"])
+def test_dense_solver_parity(pkg, greens_small, method):
+    A, B, Ad, Bd = greens_small
+    ref, H, it_tol, x_tol = _oracle_with_spread(method + "_rq", A, B, tol=1e-8, maxit=1000)
+    r = _solve(pkg, method, True, Ad, Bd, tol=1e-8, maxit=1000)
+    _check_parity(r, ref, H, it_tol, x_tol)
+
+
+@pytest.mark.parametrize("method", ["cocg", "cocr"])
+def test_mixed_precision_config1(pkg, cfg1, method):
+    A, B, Ad, Bd = cfg1
+    ref = O.solve_block(method + "_rq", A, B, tol=1e-12, maxit=4000)
+    r = _solve(pkg, method, True, Ad, Bd, tol=1e-10, maxit=4000, precision="mixed")
+    assert r.status == pkg.BLK_CONVERGED, r.status_name
+    assert r.true_relres <= 1e-10
+    assert O.true_relres(A, B, r.X.cpu().numpy()) <= 1.01e-10
+    # error against the FP64 oracle solution: both residuals are ~1e-10..1e-12
+    err = _relerr(r.X.cpu().numpy(), ref.X)
+    print(f"mixed {method}: iters={r.iters} trr={r.true_relres:.2e} |X-X_oracle|/|X_oracle|={err:.2e}")
+    assert err < 1e-6
+
+
+def test_mixed_precision_dense(pkg, greens_small):
+    A, B, Ad, Bd = greens_small
+    ref = O.bl_cocr_rq(A, B, tol=1e-12, maxit=2000)
+    r = pkg.blk_cocr_solve(Ad, Bd, tol=1e-8, maxit=2000, precision="mixed")
+    assert r.status == pkg.BLK_CONVERGED
+    assert r.true_relres <= 1e-8
+    assert _relerr(r.X.cpu().numpy(), ref.X) < 1e-5
