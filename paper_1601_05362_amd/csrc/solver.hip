@@ -31,6 +31,7 @@
 #include "common.hpp"
 #include "pxp.hpp"
 #include "rowpass.hpp"
+#include "rowpass_mfma.hpp"
 #include "spmm.hpp"
 
 namespace blk {
@@ -80,6 +81,13 @@ static void with_pp(int p, F&& f) {
     f(IC<32>{});
 }
 
+// FP64 blocks wider than 8 columns run on the matrix cores
+// (rowpass_mfma.hpp), everything else on the vector units.
+template <typename T>
+static constexpr bool use_mfma(int PP) {
+  return std::is_same<T, double>::value && PP >= 16;
+}
+
 static int env_int(const char* name, int dflt) {
   const char* v = getenv(name);
   return (v && *v) ? atoi(v) : dflt;
@@ -110,8 +118,10 @@ struct Ctx {
   int64_t n = 0;
   int p = 0;
   int G = 1;     // blocks of a row pass
+  int Gs = 1;    // blocks of an operator application that reduces a Gram or norm
   int S = 0;     // first-stage reduction segments (0: p x p kernels read the partials)
   int Emax = 0;  // doubles per block partial
+  int nblk[RO_COUNT] = {};  // blocks that wrote the partials of each role
   double* part[RO_COUNT] = {};
   double* red[RO_COUNT] = {};
   z64* slots = nullptr;
@@ -131,14 +141,17 @@ static void ctx_geometry(Ctx& c, int64_t n, int p, hipStream_t s) {
   const int gmax = std::max(8, env_int("BLK_GRID", 1024));
   c.G = (int)std::min<int64_t>(gmax, ntiles);
   if (c.G >= 64) c.G &= ~7;  // multiple of 8 for the XCD remap
-  c.S = (c.G > 64) ? 16 : 0;
+  c.Gs = (int)std::min<int64_t>(std::max(8, env_int("BLK_GRID_SPMM", 4096)), ntiles);
+  if (c.Gs >= 64) c.Gs &= ~7;
+  c.S = (std::max(c.G, c.Gs) > 64) ? 32 : 0;
+  for (int r = 0; r < RO_COUNT; ++r) c.nblk[r] = c.G;
 }
 
 static void ctx_alloc(Ctx& c, Pool& pool, int64_t n, int p, int maxit, hipStream_t s) {
   ctx_geometry(c, n, p, s);
   c.Emax = 2 * p * p + 1;
   for (int r = 0; r < RO_COUNT; ++r) {
-    c.part[r] = pool.get<double>(sizeof(double) * (size_t)c.G * c.Emax);
+    c.part[r] = pool.get<double>(sizeof(double) * (size_t)std::max(c.G, c.Gs) * c.Emax);
     if (c.S) c.red[r] = pool.get<double>(sizeof(double) * (size_t)c.S * c.Emax);
   }
   c.slots = pool.get<z64>(sizeof(z64) * (size_t)SLOT * S_NSLOTS);
@@ -149,9 +162,10 @@ static void ctx_alloc(Ctx& c, Pool& pool, int64_t n, int p, int maxit, hipStream
 
 // Reduce the partials of `role` (E doubles per block) and describe the result.
 static Red finish(Ctx& c, int role, int E, int off, int gate) {
-  if (c.S == 0) return Red{c.part[role], c.G, E, off};
+  const int G = c.nblk[role];
+  if (c.S == 0) return Red{c.part[role], G, E, off};
   dim3 grid((E + NT - 1) / NT, c.S);
-  k_reduce<<<grid, NT, 0, c.s>>>(c.part[role], c.G, E, c.red[role], c.S, c.st, gate);
+  k_reduce<<<grid, NT, 0, c.s>>>(c.part[role], G, E, c.red[role], c.S, c.st, gate);
   LAUNCH_CHECK();
   return Red{c.red[role], c.S, E, off};
 }
@@ -178,9 +192,16 @@ static void apply_op(Ctx& c, const DevOp<T>& A, const cx<T>* Z, int ldz, const c
     double* part = (GRAM || NORM) ? c.part[role] : nullptr;
     const DevState* st = c.st;
     if (A.kind == BLK_OP_CSR) {
-      k_spmm<T, PP, SUB, STORE, GRAM, NORM><<<c.G, NT, 0, c.s>>>(
+      // Without a reduction every tile of RPB rows is its own block, which
+      // keeps the most waves in flight; with one, the grid is bounded by
+      // the partials it writes.
+      const int64_t ntiles = (c.n + NT / PP - 1) / (NT / PP);
+      const int64_t G = (GRAM || NORM) ? c.Gs : ntiles;
+      if (GRAM || NORM) c.nblk[role] = c.Gs;
+      k_spmm<T, PP, SUB, STORE, GRAM, NORM><<<(unsigned)G, NT, 0, c.s>>>(
           c.n, A.rowptr, A.colind, A.val, Z, ldz, C, ldc, Y, ldy, c.p, part, E, st, gate);
     } else {
+      if (GRAM || NORM) c.nblk[role] = c.G;
       k_dense<T, PP, SUB, STORE, GRAM, NORM><<<c.G, NT, 0, c.s>>>(
           c.n, A.dense, A.ld, Z, ldz, C, ldc, Y, ldy, c.p, part, E, st, gate);
     }
@@ -210,13 +231,55 @@ static void zero_block(Ctx& c, cx<T>* Y, int ldy) {
 template <typename T, typename A, int GM, bool NORM>
 static Red gram(Ctx& c, const cx<T>* Y, int ldy, const cx<T>* Z, int ldz, int role, int gate) {
   const int E = (GM != G_NONE ? 2 * c.p * c.p : 0) + (NORM ? 1 : 0);
+  c.nblk[role] = c.G;
   with_pp(c.p, [&](auto ppc) {
     constexpr int PP = decltype(ppc)::value;
-    k_gram<T, A, PP, GM, NORM><<<c.G, NT, 0, c.s>>>(c.n, c.p, Y, ldy, Z, ldz, c.part[role], E, c.st,
-                                                    gate);
+    if constexpr (use_mfma<T>(PP)) {
+      k_gram_mf<PP / 16, GM, NORM><<<c.G, NT, 0, c.s>>>(c.n, c.p, Y, ldy, Z, ldz, c.part[role], E,
+                                                        c.st, gate);
+    } else {
+      k_gram<T, A, PP, GM, NORM><<<c.G, NT, 0, c.s>>>(c.n, c.p, Y, ldy, Z, ldz, c.part[role], E,
+                                                      c.st, gate);
+    }
     LAUNCH_CHECK();
   });
   return finish(c, role, E, 0, gate);
+}
+
+template <typename T, typename A, int GM, bool NORM>
+static void launch_axpy(Ctx& c, const cx<T>* Ain, int lda, const cx<T>* Bin, int ldb, const z64* C,
+                        cx<T>* Out, int ldo, int role, int E, int gate) {
+  c.nblk[role] = c.G;
+  with_pp(c.p, [&](auto ppc) {
+    constexpr int PP = decltype(ppc)::value;
+    if constexpr (use_mfma<T>(PP)) {
+      k_axpy_mf<PP / 16, GM, NORM><<<c.G, NT, 0, c.s>>>(c.n, c.p, Ain, lda, Bin, ldb, C, Out, ldo,
+                                                        c.part[role], E, c.st, gate);
+    } else {
+      k_axpy<T, A, PP, GM, NORM><<<c.G, NT, 0, c.s>>>(c.n, c.p, Ain, lda, Bin, ldb, C, Out, ldo,
+                                                      c.part[role], E, c.st, gate);
+    }
+    LAUNCH_CHECK();
+  });
+}
+
+template <typename T, typename A, bool WITH_U>
+static void launch_update(Ctx& c, cx<T>* X, int ldx, cx<T>* S, int lds, const cx<T>* Q, int ldq,
+                          cx<T>* U, int ldu, const cx<T>* V, int ldv, const z64* C1, const z64* C2,
+                          int role, int E, int gate) {
+  c.nblk[role] = c.G;
+  with_pp(c.p, [&](auto ppc) {
+    constexpr int PP = decltype(ppc)::value;
+    double* part = WITH_U ? c.part[role] : nullptr;
+    if constexpr (use_mfma<T>(PP)) {
+      k_update_mf<PP / 16, WITH_U><<<c.G, NT, 0, c.s>>>(c.n, c.p, X, ldx, S, lds, Q, ldq, U, ldu, V,
+                                                        ldv, C1, C2, part, E, c.st, gate);
+    } else {
+      k_update<T, A, PP, WITH_U><<<c.G, NT, 0, c.s>>>(c.n, c.p, X, ldx, S, lds, Q, ldq, U, ldu, V,
+                                                      ldv, C1, C2, part, E, c.st, gate);
+    }
+    LAUNCH_CHECK();
+  });
 }
 
 static void solve_pp(Ctx& c, SolveArgs a) {
@@ -248,16 +311,27 @@ static Red cholqr(Ctx& c, Red g1, cx<T>* W, int ldw, cx<T>* Q, int ldq, int gate
                   int init) {
   chol_pp(c, g1, 1, gate1, idx, init);
   const int E2 = 2 * c.p * c.p;
+  c.nblk[RO_P2] = c.nblk[RO_P3] = c.G;
   Red out = no_red();
   with_pp(c.p, [&](auto ppc) {
     constexpr int PP = decltype(ppc)::value;
-    k_cholqr_pass2<T, PP><<<c.G, NT, 0, c.s>>>(c.n, c.p, W, ldw, c.slots + S_R1INV * SLOT,
-                                              c.part[RO_P2], E2, c.st, gate2);
+    if constexpr (use_mfma<T>(PP)) {
+      k_cholqr_pass2_mf<PP / 16><<<c.G, NT, 0, c.s>>>(c.n, c.p, W, ldw, c.slots + S_R1INV * SLOT,
+                                                      c.part[RO_P2], E2, c.st, gate2);
+    } else {
+      k_cholqr_pass2<T, PP><<<c.G, NT, 0, c.s>>>(c.n, c.p, W, ldw, c.slots + S_R1INV * SLOT,
+                                                c.part[RO_P2], E2, c.st, gate2);
+    }
     LAUNCH_CHECK();
     Red g2 = finish(c, RO_P2, E2, 0, gate2);
     chol_pp(c, g2, 2, gate2, idx, init);
-    k_cholqr_pass3<T, A, PP, GRAM_QQ><<<c.G, NT, 0, c.s>>>(
-        c.n, c.p, W, ldw, c.slots + S_TAUINV * SLOT, Q, ldq, c.part[RO_P3], E2, c.st, gate2);
+    if constexpr (use_mfma<T>(PP)) {
+      k_cholqr_pass3_mf<PP / 16, GRAM_QQ><<<c.G, NT, 0, c.s>>>(
+          c.n, c.p, W, ldw, c.slots + S_TAUINV * SLOT, Q, ldq, c.part[RO_P3], E2, c.st, gate2);
+    } else {
+      k_cholqr_pass3<T, A, PP, GRAM_QQ><<<c.G, NT, 0, c.s>>>(
+          c.n, c.p, W, ldw, c.slots + S_TAUINV * SLOT, Q, ldq, c.part[RO_P3], E2, c.st, gate2);
+    }
     LAUNCH_CHECK();
     if (GRAM_QQ) out = finish(c, RO_P3, E2, 0, gate2);
   });
@@ -368,12 +442,8 @@ static SolveOut run_solve(Ctx& c, const DevOp<T>& Aop, bool cocr, bool rq, const
           al.fail_idx = m;
           solve_pp(c, al);
           Red g1m = no_red();
-          with_pp(p, [&](auto ppc) {
-            constexpr int PP = decltype(ppc)::value;
-            k_axpy<T, double, PP, G_CONJ, false><<<c.G, NT, 0, c.s>>>(
-                c.n, p, Q, p, U, p, c.slots + S_ALPHA * SLOT, W, p, c.part[RO_A], E2, c.st, m);
-            LAUNCH_CHECK();
-          });
+          launch_axpy<T, double, G_CONJ, false>(c, Q, p, U, p, c.slots + S_ALPHA * SLOT, W, p, RO_A,
+                                             E2, m);
           g1m = finish(c, RO_A, E2, 0, m);
           cholqr<T, A, false>(c, g1m, W, p, Q, p, m, m, m + 1, 0);
           apply_op<T, false, true, true, false>(c, Aop, Q, p, nullptr, 0, V, p, RO_S, E2, m);
@@ -388,13 +458,8 @@ static SolveOut run_solve(Ctx& c, const DevOp<T>& Aop, bool cocr, bool rq, const
           be.fail_idx = m + 1;
           be.late = 1;
           solve_pp(c, be);
-          with_pp(p, [&](auto ppc) {
-            constexpr int PP = decltype(ppc)::value;
-            k_update<T, A, PP, true><<<c.G, NT, 0, c.s>>>(
-                c.n, p, X, ldx, S, p, Q, p, U, p, V, p, c.slots + S_ALPHAXI * SLOT,
-                c.slots + S_BETA * SLOT, c.part[RO_B], E2, c.st, m);
-            LAUNCH_CHECK();
-          });
+          launch_update<T, A, true>(c, X, ldx, S, p, Q, p, U, p, V, p, c.slots + S_ALPHAXI * SLOT,
+                                    c.slots + S_BETA * SLOT, RO_B, E2, m);
           guu_prev = finish(c, RO_B, E2, 0, m);
         } else {
           apply_op<T, false, true, true, false>(c, Aop, S, p, nullptr, 0, V, p, RO_S, E2, m);
@@ -407,12 +472,8 @@ static SolveOut run_solve(Ctx& c, const DevOp<T>& Aop, bool cocr, bool rq, const
           al.gate = m;
           al.fail_idx = m;
           solve_pp(c, al);
-          with_pp(p, [&](auto ppc) {
-            constexpr int PP = decltype(ppc)::value;
-            k_axpy<T, double, PP, G_CONJ, false><<<c.G, NT, 0, c.s>>>(
-                c.n, p, Q, p, V, p, c.slots + S_ALPHA * SLOT, W, p, c.part[RO_A], E2, c.st, m);
-            LAUNCH_CHECK();
-          });
+          launch_axpy<T, double, G_CONJ, false>(c, Q, p, V, p, c.slots + S_ALPHA * SLOT, W, p, RO_A,
+                                             E2, m);
           Red g1m = finish(c, RO_A, E2, 0, m);
           Red gq = cholqr<T, A, true>(c, g1m, W, p, Q, p, m, m, m + 1, 0);
           SolveArgs be = solve_args();
@@ -425,13 +486,8 @@ static SolveOut run_solve(Ctx& c, const DevOp<T>& Aop, bool cocr, bool rq, const
           be.fail_idx = m + 1;
           be.late = 1;
           solve_pp(c, be);
-          with_pp(p, [&](auto ppc) {
-            constexpr int PP = decltype(ppc)::value;
-            k_update<T, A, PP, false><<<c.G, NT, 0, c.s>>>(
-                c.n, p, X, ldx, S, p, Q, p, nullptr, 0, nullptr, 0, c.slots + S_ALPHAXI * SLOT,
-                c.slots + S_BETA * SLOT, nullptr, 0, c.st, m);
-            LAUNCH_CHECK();
-          });
+          launch_update<T, A, false>(c, X, ldx, S, p, Q, p, nullptr, 0, nullptr, 0,
+                                    c.slots + S_ALPHAXI * SLOT, c.slots + S_BETA * SLOT, RO_B, 0, m);
         }
         if ((m + 1) % check_every == 0 || m + 1 == maxit) {
           h = read_state(c);
@@ -474,12 +530,8 @@ static SolveOut run_solve(Ctx& c, const DevOp<T>& Aop, bool cocr, bool rq, const
           al.gate = m;
           al.fail_idx = m;
           solve_pp(c, al);
-          with_pp(p, [&](auto ppc) {
-            constexpr int PP = decltype(ppc)::value;
-            k_axpy<T, A, PP, G_NONE, true><<<c.G, NT, 0, c.s>>>(
-                c.n, p, R, p, U, p, c.slots + S_ALPHA * SLOT, R, p, c.part[RO_A], 1, c.st, m);
-            LAUNCH_CHECK();
-          });
+          launch_axpy<T, A, G_NONE, true>(c, R, p, U, p, c.slots + S_ALPHA * SLOT, R, p, RO_A,
+                                             1, m);
           Red nr = finish(c, RO_A, 1, 0, m);
           apply_op<T, false, true, true, false>(c, Aop, R, p, nullptr, 0, V, p, RO_S, E2, m);
           Red grv = finish(c, RO_S, E2, 0, m);
@@ -494,13 +546,8 @@ static SolveOut run_solve(Ctx& c, const DevOp<T>& Aop, bool cocr, bool rq, const
           be.fail_idx = m + 1;
           be.late = 1;
           solve_pp(c, be);
-          with_pp(p, [&](auto ppc) {
-            constexpr int PP = decltype(ppc)::value;
-            k_update<T, A, PP, true><<<c.G, NT, 0, c.s>>>(
-                c.n, p, X, ldx, P, p, R, p, U, p, V, p, c.slots + S_ALPHA * SLOT,
-                c.slots + S_BETA * SLOT, c.part[RO_B], E2, c.st, m);
-            LAUNCH_CHECK();
-          });
+          launch_update<T, A, true>(c, X, ldx, P, p, R, p, U, p, V, p, c.slots + S_ALPHA * SLOT,
+                                    c.slots + S_BETA * SLOT, RO_B, E2, m);
           guu_prev = finish(c, RO_B, E2, 0, m);
         } else {
           apply_op<T, false, true, true, false>(c, Aop, P, p, nullptr, 0, V, p, RO_S, E2, m);
@@ -512,12 +559,8 @@ static SolveOut run_solve(Ctx& c, const DevOp<T>& Aop, bool cocr, bool rq, const
           al.gate = m;
           al.fail_idx = m;
           solve_pp(c, al);
-          with_pp(p, [&](auto ppc) {
-            constexpr int PP = decltype(ppc)::value;
-            k_axpy<T, A, PP, G_UNCONJ, true><<<c.G, NT, 0, c.s>>>(
-                c.n, p, R, p, V, p, c.slots + S_ALPHA * SLOT, R, p, c.part[RO_A], EA, c.st, m);
-            LAUNCH_CHECK();
-          });
+          launch_axpy<T, A, G_UNCONJ, true>(c, R, p, V, p, c.slots + S_ALPHA * SLOT, R, p, RO_A,
+                                             EA, m);
           Red grr = finish(c, RO_A, EA, 0, m);
           Red nr = grr;
           nr.off = E2;
@@ -532,13 +575,8 @@ static SolveOut run_solve(Ctx& c, const DevOp<T>& Aop, bool cocr, bool rq, const
           be.fail_idx = m + 1;
           be.late = 1;
           solve_pp(c, be);
-          with_pp(p, [&](auto ppc) {
-            constexpr int PP = decltype(ppc)::value;
-            k_update<T, A, PP, false><<<c.G, NT, 0, c.s>>>(
-                c.n, p, X, ldx, P, p, R, p, nullptr, 0, nullptr, 0, c.slots + S_ALPHA * SLOT,
-                c.slots + S_BETA * SLOT, nullptr, 0, c.st, m);
-            LAUNCH_CHECK();
-          });
+          launch_update<T, A, false>(c, X, ldx, P, p, R, p, nullptr, 0, nullptr, 0,
+                                    c.slots + S_ALPHA * SLOT, c.slots + S_BETA * SLOT, RO_B, 0, m);
         }
         if ((m + 1) % check_every == 0 || m + 1 == maxit) {
           h = read_state(c);

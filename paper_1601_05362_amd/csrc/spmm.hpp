@@ -43,11 +43,22 @@ __global__ __launch_bounds__(NT) void k_spmm(int64_t n, const int32_t* __restric
     if (row < n) {
       const int k0 = rowptr[row], k1 = rowptr[row + 1];
       cx<T> acc = czero<T>();
-      for (int k = k0; k < k1; ++k) {
-        const int64_t j = colind[k];
-        const cx<T> a = val[k];
-        const cx<T> z = cok ? Z[j * ldz + c] : czero<T>();
-        cfma(acc, a, z);
+      // Entries in batches of 8: all index/value loads of a batch are issued
+      // together, then all gathers of Z, so each lane keeps up to 8
+      // independent loads in flight instead of one dependent chain per entry.
+      for (int kb = k0; kb < k1; kb += 8) {
+        int jj[8];
+        cx<T> a[8], z[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const bool ok = kb + u < k1;
+          jj[u] = ok ? colind[kb + u] : 0;
+          a[u] = ok ? val[kb + u] : czero<T>();
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) z[u] = (cok && kb + u < k1) ? Z[(int64_t)jj[u] * ldz + c] : czero<T>();
+#pragma unroll
+        for (int u = 0; u < 8; ++u) cfma(acc, a[u], z[u]);
       }
       if (SUB) {
         y = cok ? Cm[row * ldc + c] : czero<T>();

@@ -161,12 +161,15 @@ def _check_parity(r, ref, horizon=50, iters_tol=None, x_tol=1e-7):
     assert r.status == ref.status
 
 
-def _oracle_with_spread(name, A, B, X0=None, tol=1e-8, maxit=1000, runs=4):
+def _oracle_with_spread(name, A, B, X0=None, tol=1e-8, maxit=1000, runs=10):
     """The oracle's result plus how far rounding alone moves it: rerun on B
     perturbed at 1e-15 relative.  Returns (ref, horizon, iters_tol, x_tol):
     the history horizon over which the perturbed runs still agree to 1e-11
-    (capped at 50), and tolerances of twice the observed spread (at least 2%
-    of the count and 1e-7 in X)."""
+    (capped at 50), and tolerances of three times the observed spread (at
+    least 2% of the count and 1e-7 in X).  The plain variants' counts scatter with
+    occasional outliers far beyond a few samples' spread (e.g. 47 -> 62 at
+    p = 16 on the 3D Helmholtz operator), so for them the count bound is at
+    least 25%."""
     ref = O.solve_block(name, A, B, X0=X0, tol=tol, maxit=maxit)
     rng = np.random.default_rng(123)
     horizon, it_spread, x_spread = 50, 0, 0.0
@@ -180,8 +183,9 @@ def _oracle_with_spread(name, A, B, X0=None, tol=1e-8, maxit=1000, runs=4):
             horizon = min(horizon, int(bad[0]) - 1)
         it_spread = max(it_spread, abs(r.iters - ref.iters))
         x_spread = max(x_spread, _relerr(r.X, ref.X))
-    iters_tol = max(2, math.floor(0.02 * ref.iters), 2 * it_spread)
-    return ref, max(horizon, 1), iters_tol, max(1e-7, 2 * x_spread)
+    frac = 0.02 if name.endswith("_rq") else 0.25
+    iters_tol = max(2, math.ceil(frac * ref.iters), 3 * it_spread)
+    return ref, max(horizon, 1), iters_tol, max(1e-7, 3 * x_spread)
 
 
 @pytest.mark.parametrize("method,rq", VARIANTS)
@@ -339,3 +343,40 @@ def test_mixed_precision_dense(pkg, greens_small):
     assert r.status == pkg.BLK_CONVERGED
     assert r.true_relres <= 1e-8
     assert _relerr(r.X.cpu().numpy(), ref.X) < 1e-5
+
+
+WIDE_CASES = [(m, rq, p) for (m, rq) in VARIANTS for p in (12, 16, 32) if rq or p <= 16]
+
+
+@pytest.mark.parametrize("method,rq,p", WIDE_CASES)
+def test_wide_block_parity(pkg, dev, method, rq, p):
+    """p > 8 runs the block updates and Grams on the FP64 matrix cores.
+
+    The plain variants are run up to p = 16 only: at p = 32 their p x p forms
+    go near-singular at rounding-dependent iterations (the oracle itself
+    breaks down or converges depending on a 1e-15 perturbation of B), which is
+    the loss of independence that residual orthonormalization removes."""
+    A = W.config2_operator(12)  # 3D Helmholtz, n = 1728, k h = 0.25
+    B = W.cgauss(A.n, p, seed=p)
+    Ad = pkg.CsrOperator.from_arrays(A.rowptr, A.colind, A.val, device=dev)
+    # 1e-9 is crossed on the steep part of the convergence curve; near 1e-10
+    # the p = 32 histories plateau at the attainable accuracy, where the
+    # crossing iteration is set by rounding.
+    ref, H, it_tol, x_tol = _oracle_with_spread(ORACLE_NAME[(method, rq)], A, B, tol=1e-9, maxit=400)
+    r = _solve(pkg, method, rq, Ad, torch.as_tensor(B, device=dev), tol=1e-9, maxit=400)
+    _check_parity(r, ref, H, it_tol, x_tol)
+
+
+@pytest.mark.parametrize("p", [16, 24, 32])
+def test_wide_block_kernels(pkg, dev, p):
+    """Gram and thin QR at tile-ragged n for the matrix-core kernels."""
+    n = 1000 + 7
+    Y = W.cgauss(n, p, seed=1)
+    Z = W.cgauss(n, p, seed=2)
+    Yd, Zd = torch.as_tensor(Y, device=dev), torch.as_tensor(Z, device=dev)
+    assert _relerr(pkg.blk_gram_z(Yd, Zd, conj=False), Y.T @ Z) < 1e-13
+    assert _relerr(pkg.blk_gram_z(Yd, Zd, conj=True), Y.conj().T @ Z) < 1e-13
+    Q, R = pkg.blk_thin_qr_z(Yd)
+    Qr, Rr = O.thin_qr_pos(Y)
+    assert _relerr(R, Rr) < 1e-12
+    assert _relerr(Q.cpu().numpy(), Qr) < 1e-12
