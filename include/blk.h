@@ -80,7 +80,12 @@ typedef struct {
                           (default: maxit). */
   int32_t check_every; /* iterations between host convergence checks
                           (default 16); does not change results. */
-  int32_t reserved;
+  int32_t refine;      /* restarts allowed when the monitored residual has
+                          reached tol but the true FP64 residual ||B - A X||_F
+                          / ||B||_F has not (rounding drift of the recurrences);
+                          each restart solves again from the current X.
+                          0 (default): stop on the monitored residual as the
+                          algorithms do. */
   void *stream;        /* hipStream_t, NULL = legacy default stream. */
 } blk_opts;
 
@@ -115,6 +120,8 @@ typedef enum {
  *              relative residual of iterate m, m = 0..*iters.  BLK_MIXED
  *              writes the inner estimates scaled to ||B||_F, one per inner
  *              iteration, so it then needs room for maxit + 1 entries too.
+ *              After a refine restart the entries continue with the
+ *              restarted run's monitored residuals (relative to ||B||_F).
  *   iters      [host] number of iterations done (total inner iterations
  *              for BLK_MIXED), or NULL.
  *   true_relres [host] ||B - A X||_F / ||B||_F of the returned X computed in

@@ -153,7 +153,7 @@ class SolveResult:
 
 
 def _solve(fn_name: str, A, B, X0, tol, maxit, rq, precision, inner_tol, inner_maxit,
-           check_every, out):
+           check_every, out, refine=0):
     lib = _lib()
     dev = B.device
     ldb = _block(B, "B")
@@ -170,7 +170,7 @@ def _solve(fn_name: str, A, B, X0, tol, maxit, rq, precision, inner_tol, inner_m
     op = A.as_c()
     with torch.cuda.device(dev):
         opts = _capi.BlkOpts(1 if rq else 0, prec, float(inner_tol), int(inner_maxit),
-                             int(check_every), 0, _stream(dev))
+                             int(check_every), int(refine), _stream(dev))
         rc = getattr(lib, fn_name)(
             C.byref(op), p, _ptr(B), ldb, _ptr(X0), ldx0, float(tol), int(maxit), C.byref(opts),
             _ptr(X), ldx, hist.ctypes.data_as(C.POINTER(C.c_double)), C.byref(iters),
@@ -183,19 +183,21 @@ def _solve(fn_name: str, A, B, X0, tol, maxit, rq, precision, inner_tol, inner_m
 
 
 def blk_cocg_solve(A, B, X0=None, tol=1e-8, maxit=1000, *, rq=True, precision="fp64",
-                   inner_tol=1e-3, inner_maxit=0, check_every=16, out=None) -> SolveResult:
+                   inner_tol=1e-3, inner_maxit=0, check_every=16, refine=0,
+                   out=None) -> SolveResult:
     """Block COCG (rq=False) or block COCG with residual orthonormalization
     (rq=True, Algorithm 2) for A X = B."""
     return _solve("blk_cocg_solve", A, B, X0, tol, maxit, rq, precision, inner_tol,
-                  inner_maxit, check_every, out)
+                  inner_maxit, check_every, out, refine)
 
 
 def blk_cocr_solve(A, B, X0=None, tol=1e-8, maxit=1000, *, rq=True, precision="fp64",
-                   inner_tol=1e-3, inner_maxit=0, check_every=16, out=None) -> SolveResult:
+                   inner_tol=1e-3, inner_maxit=0, check_every=16, refine=0,
+                   out=None) -> SolveResult:
     """Block COCR (rq=False, Algorithm 1) or block COCR with residual
     orthonormalization (rq=True, Algorithm 3) for A X = B."""
     return _solve("blk_cocr_solve", A, B, X0, tol, maxit, rq, precision, inner_tol,
-                  inner_maxit, check_every, out)
+                  inner_maxit, check_every, out, refine)
 
 
 def blk_spmm_z(A, Z: torch.Tensor, C_: torch.Tensor | None = None, out=None, gram=False):

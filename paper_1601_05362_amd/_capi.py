@@ -45,7 +45,7 @@ class BlkOpts(C.Structure):
         ("inner_tol", C.c_double),
         ("inner_maxit", C.c_int32),
         ("check_every", C.c_int32),
-        ("reserved", C.c_int32),
+        ("refine", C.c_int32),
         ("stream", C.c_void_p),
     ]
 

@@ -22,10 +22,10 @@ namespace blk {
 // the eight XCDs round-robin, so logical block numbers are remapped to give
 // each XCD one contiguous slab of rows (neighbour rows of a stencil then hit
 // the same L2).
-__device__ inline void tile_range(int64_t ntiles, int64_t& t0, int64_t& t1) {
+__device__ inline void tile_range(int64_t ntiles, int64_t& t0, int64_t& t1, bool remap = true) {
   const int G = gridDim.x;
   const int b = blockIdx.x;
-  const int lb = ((G & 7) == 0) ? (b & 7) * (G >> 3) + (b >> 3) : b;
+  const int lb = (remap && (G & 7) == 0) ? (b & 7) * (G >> 3) + (b >> 3) : b;
   const int64_t per = (ntiles + G - 1) / G;
   t0 = (int64_t)lb * per;
   t1 = t0 + per < ntiles ? t0 + per : ntiles;

@@ -198,8 +198,11 @@ static void apply_op(Ctx& c, const DevOp<T>& A, const cx<T>* Z, int ldz, const c
       const int64_t ntiles = (c.n + NT / PP - 1) / (NT / PP);
       const int64_t G = (GRAM || NORM) ? c.Gs : ntiles;
       if (GRAM || NORM) c.nblk[role] = c.Gs;
+      // one tile per block: natural block order (consecutive tiles on
+      // different XCDs); bounded grids: one contiguous slab per XCD
+      const int remap = (GRAM || NORM) ? 1 : env_int("BLK_SPMM_REMAP", 0);
       k_spmm<T, PP, SUB, STORE, GRAM, NORM><<<(unsigned)G, NT, 0, c.s>>>(
-          c.n, A.rowptr, A.colind, A.val, Z, ldz, C, ldc, Y, ldy, c.p, part, E, st, gate);
+          c.n, A.rowptr, A.colind, A.val, Z, ldz, C, ldc, Y, ldy, c.p, part, E, st, gate, remap);
     } else {
       if (GRAM || NORM) c.nblk[role] = c.G;
       k_dense<T, PP, SUB, STORE, GRAM, NORM><<<c.G, NT, 0, c.s>>>(
@@ -609,6 +612,23 @@ static bool blk_log() {
   return on;
 }
 
+// Restart from X while the monitored residual says converged but the true
+// FP64 residual does not (at most `refine` times, within maxit in total).
+static void refine_fp64(Ctx& c, const DevOp<double>& A64, bool cocr, bool rq, const z64* Bz, int ldb,
+                        z64* Xz, int ldx, double tol, int maxit, int check_every, int refine,
+                        double normB, Blocks<double>& bk, SolveOut& so) {
+  for (int k = 0; k < refine && so.status == ST_CONVERGED && so.iters < maxit; ++k) {
+    const double trr = true_relres(c, A64, Bz, ldb, Xz, ldx, normB);
+    if (blk_log()) fprintf(stderr, "[blk] refine check after %d iterations: true rel. residual %.3e\n", so.iters, trr);
+    if (!(trr > tol)) break;
+    SolveOut r = run_solve<double, double>(c, A64, cocr, rq, Bz, ldb, Xz, ldx, Xz, ldx, tol,
+                                           maxit - so.iters, check_every, bk);
+    for (int m = 1; m <= r.iters; ++m) so.hist.push_back(r.hist[m]);
+    so.iters += r.iters;
+    so.status = r.status;
+  }
+}
+
 // Mixed precision: FP64 residual B - A X and FP64 X, complex64 inner solves
 // of A D = R / ||R|| (iterative refinement).  A correction that makes the
 // FP64 residual grow is undone; when refinement stops paying (a worse or
@@ -729,6 +749,8 @@ static SolveOut run_mixed(Ctx& c, Pool& pool, const blk_op* A, const DevOp<doubl
     for (int i = 0; i < 5; ++i) bk64.b[i] = pool.get<z64>(sizeof(z64) * (size_t)n * pi);
     SolveOut f = run_solve<double, double>(c, A64, cocr, o.rq != 0, Bz, ldb, Xz, ldx, Xz, ldx, tol,
                                            maxit - total, o.check_every, bk64);
+    refine_fp64(c, A64, cocr, o.rq != 0, Bz, ldb, Xz, ldx, tol, maxit - total, o.check_every,
+                std::max(0, o.refine), normB, bk64, f);
     for (int k = 1; k <= f.iters && (int)so.hist.size() < hist_len; ++k) so.hist.push_back(f.hist[k]);
     total += f.iters;
     so.status = f.status;
@@ -825,6 +847,9 @@ static int solve_entry(bool cocr, const blk_op* A, int64_t p, const blk_z* B, in
       so = run_solve<double, double>(c, A64, cocr, o.rq != 0, Bz, (int)ldb, X0z, (int)ldx0, Xz,
                                      (int)ldx, tol, maxit, o.check_every, bk);
       normB = read_state(c).normB;
+      if (normB > 0.0 && std::isfinite(normB))
+        refine_fp64(c, A64, cocr, o.rq != 0, Bz, (int)ldb, Xz, (int)ldx, tol, maxit, o.check_every,
+                    std::max(0, o.refine), normB, bk, so);
     } else {
       so = run_mixed(c, pool, A, A64, cocr, o, Bz, (int)ldb, X0z, (int)ldx0, Xz, (int)ldx, tol,
                      maxit, normB);

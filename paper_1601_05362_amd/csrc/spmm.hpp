@@ -23,7 +23,7 @@ __global__ __launch_bounds__(NT) void k_spmm(int64_t n, const int32_t* __restric
                                              const cx<T>* __restrict__ Z, int ldz,
                                              const cx<T>* __restrict__ Cm, int ldc,
                                              cx<T>* __restrict__ Y, int ldy, int p, double* part,
-                                             int E, const DevState* st, int gate) {
+                                             int E, const DevState* st, int gate, int remap) {
   if (st && gate >= st->stop_iter) return;
   constexpr int RPB = NT / PP;
   __shared__ cx<T> zs[GRAM ? NT : 1];
@@ -35,7 +35,7 @@ __global__ __launch_bounds__(NT) void k_spmm(int64_t n, const int32_t* __restric
   const int lr = threadIdx.x / PP, c = threadIdx.x % PP;
   const bool cok = c < p;
   int64_t t0, t1;
-  tile_range((n + RPB - 1) / RPB, t0, t1);
+  tile_range((n + RPB - 1) / RPB, t0, t1, remap != 0);
   for (int64_t t = t0; t < t1; ++t) {
     const int64_t row = t * RPB + lr;
     cx<T> y = czero<T>();

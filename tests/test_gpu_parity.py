@@ -380,3 +380,29 @@ def test_wide_block_kernels(pkg, dev, p):
     Qr, Rr = O.thin_qr_pos(Y)
     assert _relerr(R, Rr) < 1e-12
     assert _relerr(Q.cpu().numpy(), Qr) < 1e-12
+
+
+@pytest.mark.parametrize("method", ["cocg", "cocr"])
+def test_refine_restarts(pkg, cfg1, method):
+    """refine > 0 restarts from X only while the true residual lags the
+    monitored one; the restarted run continues the first run's history."""
+    A, B, Ad, Bd = cfg1
+    base = _solve(pkg, method, True, Ad, Bd, tol=1e-8, maxit=2000)
+    same = _solve(pkg, method, True, Ad, Bd, tol=1e-8, maxit=2000, refine=2)
+    assert base.true_relres <= 1e-8
+    assert same.iters == base.iters and np.array_equal(same.hist, base.hist)
+    assert torch.equal(same.X, base.X)
+    # a tolerance near the attainable accuracy
+    tol = 1e-13
+    t0 = _solve(pkg, method, True, Ad, Bd, tol=tol, maxit=3000)
+    t2 = _solve(pkg, method, True, Ad, Bd, tol=tol, maxit=3000, refine=2)
+    print(f"{method}: refine=0 iters={t0.iters} {t0.status_name} trr={t0.true_relres:.2e}; "
+          f"refine=2 iters={t2.iters} {t2.status_name} trr={t2.true_relres:.2e}")
+    assert t2.iters >= t0.iters
+    assert np.array_equal(t2.hist[: t0.iters + 1], t0.hist)
+    if t0.status == pkg.BLK_CONVERGED and t0.true_relres > tol:
+        assert t2.iters > t0.iters
+        assert t2.true_relres < t0.true_relres
+    # the reported true residual is the residual of the returned X
+    trr = O.true_relres(A, B, t2.X.cpu().numpy())
+    assert abs(trr - t2.true_relres) <= 1e-6 * trr + 1e-17
