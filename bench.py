@@ -38,8 +38,9 @@ def spmm_bytes(n: int, nnz: int, p: int, cbytes: int) -> int:
     return nnz * (cbytes + 4) + 4 * (n + 1) + 2 * n * p * cbytes
 
 
+# the kernel and the host code that picks its launch shape
 SPMM_SOURCES = ["paper_1601_05362_amd/csrc/spmm.hpp", "paper_1601_05362_amd/csrc/rowpass.hpp",
-                "paper_1601_05362_amd/csrc/common.hpp"]
+                "paper_1601_05362_amd/csrc/common.hpp", "paper_1601_05362_amd/csrc/solver.hip"]
 TRAFFIC_PROFILE = "profiles/k_spmm_c128_p32_helmholtz3d_128.md"
 
 

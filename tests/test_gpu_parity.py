@@ -403,6 +403,7 @@ def test_refine_restarts(pkg, cfg1, method):
     if t0.status == pkg.BLK_CONVERGED and t0.true_relres > tol:
         assert t2.iters > t0.iters
         assert t2.true_relres < t0.true_relres
-    # the reported true residual is the residual of the returned X
+    # the reported true residual is the residual of the returned X; forming
+    # B - A X in FP64 is itself accurate to about eps |A| |X| / |B|
     trr = O.true_relres(A, B, t2.X.cpu().numpy())
-    assert abs(trr - t2.true_relres) <= 1e-6 * trr + 1e-17
+    assert abs(trr - t2.true_relres) <= 1e-6 * trr + 1e-14
