@@ -38,26 +38,78 @@ __device__ inline z64 cdiv(z64 a, z64 b) {
   }
 }
 
-// dst[p x p] = sum of the rows of a reduced Gram.
+// dst[p x p] = sum of the rows of a reduced Gram, each entry summed over the
+// rows in ascending order.  Loads are issued four rows at a time for all of
+// a thread's entries so that one workgroup keeps many in flight.
 __device__ inline void red_load(const Red r, z64* dst, int p) {
-  for (int e = threadIdx.x; e < p * p; e += NT) {
-    double re = 0.0, im = 0.0;
-    for (int s = 0; s < r.nrows; ++s) {
-      const double* src = r.base + (size_t)s * r.ld + r.off;
-      re += src[2 * e];
-      im += src[2 * e + 1];
+  constexpr int KE = (2 * PMAX * PMAX + NT - 1) / NT;
+  const int E = 2 * p * p;
+  const double* src = r.base + r.off;
+  double* d = reinterpret_cast<double*>(dst);
+  double acc[KE];
+#pragma unroll
+  for (int k = 0; k < KE; ++k) acc[k] = 0.0;
+  int s = 0;
+  for (; s + 4 <= r.nrows; s += 4) {
+    double v[4][KE];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int k = 0; k < KE; ++k) {
+        const int e = threadIdx.x + k * NT;
+        v[u][k] = e < E ? src[(size_t)(s + u) * r.ld + e] : 0.0;
+      }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int k = 0; k < KE; ++k) acc[k] += v[u][k];
+  }
+  for (; s < r.nrows; ++s)
+#pragma unroll
+    for (int k = 0; k < KE; ++k) {
+      const int e = threadIdx.x + k * NT;
+      if (e < E) acc[k] += src[(size_t)s * r.ld + e];
     }
-    dst[e] = z64{re, im};
+#pragma unroll
+  for (int k = 0; k < KE; ++k) {
+    const int e = threadIdx.x + k * NT;
+    if (e < E) d[e] = acc[k];
   }
 }
 
+// Sum of one column of a reduced scalar (rows in ascending order).
 __device__ inline double red_scalar(const Red r) {
   double s = 0.0;
-  for (int k = 0; k < r.nrows; ++k) s += r.base[(size_t)k * r.ld + r.off];
+  int k = 0;
+  for (; k + 8 <= r.nrows; k += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = r.base[(size_t)(k + u) * r.ld + r.off];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  for (; k < r.nrows; ++k) s += r.base[(size_t)k * r.ld + r.off];
   return s;
 }
 
-// C = A B for p x p row-major operands (may be LDS or global; C must not
+// C = A for p x p blocks (global <-> LDS): all of a thread's loads first.
+__device__ inline void copy_pp(const z64* A, z64* C, int p) {
+  constexpr int KE = (PMAX * PMAX + NT - 1) / NT;
+  const int E = p * p;
+  z64 v[KE];
+#pragma unroll
+  for (int k = 0; k < KE; ++k) {
+    const int e = threadIdx.x + k * NT;
+    if (e < E) v[k] = A[e];
+  }
+#pragma unroll
+  for (int k = 0; k < KE; ++k) {
+    const int e = threadIdx.x + k * NT;
+    if (e < E) C[e] = v[k];
+  }
+}
+
+// C = A B for p x p row-major operands in LDS (C may be global; it must not
 // alias A or B).  TA: use A^T.
 template <bool TA>
 __device__ inline void mm(const z64* A, const z64* B, z64* C, int p) {
@@ -67,10 +119,6 @@ __device__ inline void mm(const z64* A, const z64* B, z64* C, int p) {
     for (int k = 0; k < p; ++k) cfma(acc, TA ? A[k * p + i] : A[i * p + k], B[k * p + j]);
     C[e] = acc;
   }
-}
-
-__device__ inline void copy_pp(const z64* A, z64* C, int p) {
-  for (int e = threadIdx.x; e < p * p; e += NT) C[e] = A[e];
 }
 
 // Upper Cholesky factor in place: a = R with R^H R = G (upper triangle of a
@@ -237,6 +285,8 @@ __global__ __launch_bounds__(NT) void k_chol(CholArgs a) {
   __shared__ z64 G[SLOT];
   __shared__ z64 R[SLOT];
   __shared__ z64 Ri[SLOT];
+  __shared__ z64 T1[SLOT];
+  __shared__ z64 T2[SLOT];
   __shared__ double sh[NT / 64];
   const int p = st->p;
   z64* slots = a.slots;
@@ -288,16 +338,22 @@ __global__ __launch_bounds__(NT) void k_chol(CholArgs a) {
     copy_pp(Ri, slots + S_R1INV * SLOT, p);
     return;
   }
-  // tau = R2 R1 (into G), tau^{-1} = R1^{-1} R2^{-1}
-  mm<false>(R, slots + S_R1 * SLOT, G, p);
-  mm<false>(slots + S_R1INV * SLOT, Ri, slots + S_TAUINV * SLOT, p);
+  // stage R1, R1^{-1} and xi_m (G is free once R holds the factor)
+  copy_pp(slots + S_R1 * SLOT, T1, p);
+  copy_pp(slots + S_R1INV * SLOT, T2, p);
+  if (!a.init) copy_pp(slots + S_XI * SLOT, G, p);
   __syncthreads();
-  copy_pp(G, slots + S_TAU * SLOT, p);
+  // tau^{-1} = R1^{-1} R2^{-1}, then tau = R2 R1 (into T2)
+  mm<false>(T2, Ri, slots + S_TAUINV * SLOT, p);
+  __syncthreads();
+  mm<false>(R, T1, T2, p);
+  __syncthreads();
+  copy_pp(T2, slots + S_TAU * SLOT, p);
   // xi_{m+1} = tau xi_m (into R)
   if (a.init)
-    copy_pp(G, R, p);
+    copy_pp(T2, R, p);
   else
-    mm<false>(G, slots + S_XI * SLOT, R, p);
+    mm<false>(T2, G, R, p);
   __syncthreads();
   double n2 = 0.0;
   for (int e = threadIdx.x; e < p * p; e += NT) n2 += cabs2(R[e]);
@@ -344,6 +400,7 @@ __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
   __shared__ z64 M[SLOT];
   __shared__ z64 Rh[SLOT];
   __shared__ z64 T[SLOT];
+  __shared__ z64 X[SLOT];
   __shared__ z64 lcol[PMAX];
   __shared__ int piv;
   __shared__ double sh[NT / 64];
@@ -363,6 +420,7 @@ __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
       st->status = ST_MAXIT;
     }
   }
+  // every slot is read before save_slot (which may be mslot) is written
   if (a.mred.base != nullptr)
     red_load(a.mred, M, p);
   else
@@ -371,13 +429,15 @@ __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
     red_load(a.rred, Rh, p);
   else
     copy_pp(slots + a.rslot * SLOT, Rh, p);
+  if (a.rhs_tauT) copy_pp(slots + S_TAU * SLOT, T, p);
   __syncthreads();
   if (a.save_slot >= 0) copy_pp(Rh, slots + a.save_slot * SLOT, p);
   if (a.rhs_tauT) {
-    mm<true>(slots + S_TAU * SLOT, Rh, T, p);
+    mm<true>(T, Rh, X, p);
     __syncthreads();
-    copy_pp(T, Rh, p);
+    copy_pp(X, Rh, p);
   }
+  if (a.outxi_slot >= 0) copy_pp(slots + S_XI * SLOT, T, p);
   __syncthreads();
   const double thr = PIVOT_TOL * max_abs(M, p, sh);
   const bool ok = thr > 0.0 && lu_solve(M, Rh, p, thr, &piv, lcol);
@@ -398,7 +458,7 @@ __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
     return;
   }
   copy_pp(Rh, slots + a.out_slot * SLOT, p);
-  if (a.outxi_slot >= 0) mm<false>(Rh, slots + S_XI * SLOT, slots + a.outxi_slot * SLOT, p);
+  if (a.outxi_slot >= 0) mm<false>(Rh, T, slots + a.outxi_slot * SLOT, p);
 }
 
 // Start-up: slot <- a reduced Gram (if gred is given) and, for the plain

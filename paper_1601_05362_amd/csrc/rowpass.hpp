@@ -349,7 +349,15 @@ __global__ __launch_bounds__(NT) void k_reduce(const double* __restrict__ part, 
   if (e >= E) return;
   const int g0 = (int)((int64_t)G * s / S), g1 = (int)((int64_t)G * (s + 1) / S);
   double acc = 0.0;
-  for (int g = g0; g < g1; ++g) acc += part[(size_t)g * E + e];
+  int g = g0;
+  for (; g + 8 <= g1; g += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(size_t)(g + u) * E + e];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += v[u];
+  }
+  for (; g < g1; ++g) acc += part[(size_t)g * E + e];
   red[(size_t)s * E + e] = acc;
 }
 

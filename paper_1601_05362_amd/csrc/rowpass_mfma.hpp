@@ -23,6 +23,18 @@ namespace blk {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
+#ifndef MF_WAVES
+#define MF_WAVES 2
+#endif
+#ifndef MF_SCHED
+#define MF_SCHED 0
+#endif
+#if MF_SCHED
+#define MF_STEP_BARRIER() __builtin_amdgcn_sched_barrier(0)
+#else
+#define MF_STEP_BARRIER() ((void)0)
+#endif
+
 __device__ inline d4 mfma64(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
@@ -101,6 +113,16 @@ __device__ inline void mf_zero_D(d4 (&xr)[JB], d4 (&xi)[JB]) {
   }
 }
 
+// acc += d elementwise (D layout).
+template <int JB>
+__device__ inline void mf_add_D(d4 (&ar)[JB], d4 (&ai)[JB], const d4 (&dr)[JB], const d4 (&di)[JB]) {
+#pragma unroll
+  for (int jb = 0; jb < JB; ++jb) {
+    ar[jb] += dr[jb];
+    ai[jb] += di[jb];
+  }
+}
+
 template <int JB>
 __device__ inline void mf_store_D(z64* X, int ld, int64_t r0, int64_t n, int p, const d4 (&xr)[JB],
                                   const d4 (&xi)[JB]) {
@@ -136,6 +158,9 @@ __device__ inline void mf_mma(d4 (&cr)[JB], d4 (&ci)[JB], const double (&ar)[4 *
       cr[jb] = mfma64(ai[s], bn, cr[jb]);
       ci[jb] = mfma64(ar[s], bi, ci[jb]);
       ci[jb] = mfma64(ai[s], br, ci[jb]);
+      // keep the coefficient reads next to their products: batching them
+      // ahead would hold ~100 registers and cut occupancy
+      MF_STEP_BARRIER();
     }
   }
 }
@@ -252,10 +277,11 @@ constexpr int mf_smem_doubles() {
                                                                    : mf_scratch_doubles<JB>();
 }
 
-// Out = Ain - Bin C, Gram of Out (GM), ||Out||^2 (NORM).  Out may alias Ain.
+// Out = Ain + sign Bin C, Gram of Out (GM), ||Out||^2 (NORM).  Out may alias
+// Ain or Bin (each wave reads its whole tile before writing it).
 template <int JB, int GM, bool NORM>
-__global__ __launch_bounds__(NT, 2) void k_axpy_mf(int64_t n, int p, const z64* Ain, int lda,
-                                                const z64* __restrict__ Bin, int ldb, const z64* C,
+__global__ __launch_bounds__(NT, MF_WAVES) void k_axpy_mf(int64_t n, int p, const z64* Ain, int lda,
+                                                const z64* Bin, int ldb, const z64* C, double sign,
                                                 z64* Out, int ldo, double* part, int E,
                                                 const DevState* st, int gate) {
   if (gate >= st->stop_iter) return;
@@ -263,7 +289,7 @@ __global__ __launch_bounds__(NT, 2) void k_axpy_mf(int64_t n, int p, const z64* 
   __shared__ double sh[NT / 64];
   MfCoef<JB>& cf = *reinterpret_cast<MfCoef<JB>*>(smem);
   double* scratch = smem;
-  mf_load_coef<JB>(&cf, C, p, -1.0);
+  mf_load_coef<JB>(&cf, C, p, sign);
   __syncthreads();
   MfGram<JB> g;
   g.zero();
@@ -273,11 +299,15 @@ __global__ __launch_bounds__(NT, 2) void k_axpy_mf(int64_t n, int p, const z64* 
   mf_tiles(n, t0, t1);
   for (int64_t t = t0 + w; t < t1; t += NT / 64) {
     const int64_t r0 = t * 16;
+    // all loads first; the products accumulate from zero and the addend
+    // (whose loads complete under the products) joins at the end
     double ar[4 * JB], ai[4 * JB];
-    d4 cr[JB], ci[JB];
+    d4 dr[JB], di[JB], cr[JB], ci[JB];
     mf_load_A<JB>(Bin, ldb, r0, n, p, ar, ai);
-    mf_load_D<JB>(Ain, lda, r0, n, p, cr, ci);
+    mf_load_D<JB>(Ain, lda, r0, n, p, dr, di);
+    mf_zero_D<JB>(cr, ci);
     mf_mma<JB, false>(cr, ci, ar, ai, mf_opaque(&cf));
+    mf_add_D<JB>(cr, ci, dr, di);
     mf_store_D<JB>(Out, ldo, r0, n, p, cr, ci);
     if (GM == G_CONJ) g.template add<true>(cr, ci);
     if (GM == G_UNCONJ) g.template add<false>(cr, ci);
@@ -293,7 +323,7 @@ __global__ __launch_bounds__(NT, 2) void k_axpy_mf(int64_t n, int p, const z64* 
 
 // Second Cholesky-QR pass: Gram (W M)^H (W M), M upper triangular.
 template <int JB>
-__global__ __launch_bounds__(NT, 2) void k_cholqr_pass2_mf(int64_t n, int p, const z64* __restrict__ Win,
+__global__ __launch_bounds__(NT, MF_WAVES) void k_cholqr_pass2_mf(int64_t n, int p, const z64* __restrict__ Win,
                                                         int ldw, const z64* M, double* part, int E,
                                                         const DevState* st, int gate) {
   if (gate >= st->stop_iter) return;
@@ -321,7 +351,7 @@ __global__ __launch_bounds__(NT, 2) void k_cholqr_pass2_mf(int64_t n, int p, con
 
 // Third Cholesky-QR pass: Q = W M (M upper triangular), optional Q^T Q.
 template <int JB, bool GRAM>
-__global__ __launch_bounds__(NT, 2) void k_cholqr_pass3_mf(int64_t n, int p, const z64* Win, int ldw,
+__global__ __launch_bounds__(NT, MF_WAVES) void k_cholqr_pass3_mf(int64_t n, int p, const z64* Win, int ldw,
                                                         const z64* M, z64* Q, int ldq, double* part,
                                                         int E, const DevState* st, int gate) {
   if (gate >= st->stop_iter) return;
@@ -348,56 +378,46 @@ __global__ __launch_bounds__(NT, 2) void k_cholqr_pass3_mf(int64_t n, int p, con
   if (GRAM) g.template store<false>(part + (size_t)blockIdx.x * E, p, scratch);
 }
 
-// X += S C1;  S = Q + S C2;  with WITH_U: U = V + U C2 and the Gram U^T U.
-template <int JB, bool WITH_U>
-__global__ __launch_bounds__(NT, 2) void k_update_mf(int64_t n, int p, z64* X, int ldx, z64* S, int lds,
-                                                  const z64* __restrict__ Q, int ldq, z64* U, int ldu,
-                                                  const z64* __restrict__ V, int ldv, const z64* C1,
-                                                  const z64* C2, double* part, int E,
-                                                  const DevState* st, int gate) {
+// X += S C1;  S = Q + S C2.
+template <int JB>
+__global__ __launch_bounds__(NT, MF_WAVES) void k_update_mf(int64_t n, int p, z64* X, int ldx, z64* S,
+                                                         int lds, const z64* __restrict__ Q, int ldq,
+                                                         const z64* C1, const z64* C2,
+                                                         const DevState* st, int gate) {
   if (gate >= st->stop_iter) return;
   __shared__ double smem[mf_smem_doubles<JB, 2>()];
   MfCoef<JB>& cf1 = *reinterpret_cast<MfCoef<JB>*>(smem);
   MfCoef<JB>& cf2 = *reinterpret_cast<MfCoef<JB>*>(smem + mf_coef_doubles<JB>());
-  double* scratch = smem;
   mf_load_coef<JB>(&cf1, C1, p, 1.0);
   mf_load_coef<JB>(&cf2, C2, p, 1.0);
   __syncthreads();
-  MfGram<JB> g;
-  g.zero();
   const int w = threadIdx.x >> 6;
   int64_t t0, t1;
   mf_tiles(n, t0, t1);
   for (int64_t t = t0 + w; t < t1; t += NT / 64) {
     const int64_t r0 = t * 16;
-    if (WITH_U) {
-      // U phase: U = V + U C2 and its Gram
-      double ur[4 * JB], ui[4 * JB];
-      d4 vr[JB], vi[JB];
-      mf_load_A<JB>(U, ldu, r0, n, p, ur, ui);
-      mf_load_D<JB>(V, ldv, r0, n, p, vr, vi);
-      mf_mma<JB, false>(vr, vi, ur, ui, mf_opaque(&cf2));
-      mf_store_D<JB>(U, ldu, r0, n, p, vr, vi);
-      g.template add<false>(vr, vi);
-    }
-    // S phase: X += S C1, S = Q + S C2
+    // all loads first; the products accumulate from zero and the addends,
+    // whose loads complete under the products, join last
     double sr[4 * JB], si[4 * JB];
-    d4 xr[JB], xi[JB], qr[JB], qi[JB];
+    d4 xr[JB], xi[JB], qr[JB], qi[JB], ar[JB], ai[JB], br[JB], bi[JB];
     mf_load_A<JB>(S, lds, r0, n, p, sr, si);
     mf_load_D<JB>(X, ldx, r0, n, p, xr, xi);
     mf_load_D<JB>(Q, ldq, r0, n, p, qr, qi);
-    mf_mma<JB, false>(xr, xi, sr, si, mf_opaque(&cf1));
-    mf_mma<JB, false>(qr, qi, sr, si, mf_opaque(&cf2));
-    mf_store_D<JB>(X, ldx, r0, n, p, xr, xi);
-    mf_store_D<JB>(S, lds, r0, n, p, qr, qi);
+    mf_zero_D<JB>(ar, ai);
+    mf_zero_D<JB>(br, bi);
+    mf_mma<JB, false>(ar, ai, sr, si, mf_opaque(&cf1));
+    mf_mma<JB, false>(br, bi, sr, si, mf_opaque(&cf2));
+    mf_add_D<JB>(ar, ai, xr, xi);
+    mf_add_D<JB>(br, bi, qr, qi);
+    mf_store_D<JB>(X, ldx, r0, n, p, ar, ai);
+    mf_store_D<JB>(S, lds, r0, n, p, br, bi);
   }
-  if (WITH_U) g.template store<false>(part + (size_t)blockIdx.x * E, p, scratch);
 }
 
 // Gram of two blocks G = Y^T Z (GM = G_UNCONJ) or Y^H Z (G_CONJ) from D-layout
 // loads, plus ||Y||^2 (NORM).  General (non-symmetric) form: all JB x JB blocks.
 template <int JB, int GM, bool NORM>
-__global__ __launch_bounds__(NT, 2) void k_gram_mf(int64_t n, int p, const z64* __restrict__ Y, int ldy,
+__global__ __launch_bounds__(NT, MF_WAVES) void k_gram_mf(int64_t n, int p, const z64* __restrict__ Y, int ldy,
                                                 const z64* __restrict__ Z, int ldz, double* part, int E,
                                                 const DevState* st, int gate) {
   if (st && gate >= st->stop_iter) return;

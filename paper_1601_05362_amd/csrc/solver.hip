@@ -256,8 +256,8 @@ static void launch_axpy(Ctx& c, const cx<T>* Ain, int lda, const cx<T>* Bin, int
   with_pp(c.p, [&](auto ppc) {
     constexpr int PP = decltype(ppc)::value;
     if constexpr (use_mfma<T>(PP)) {
-      k_axpy_mf<PP / 16, GM, NORM><<<c.G, NT, 0, c.s>>>(c.n, c.p, Ain, lda, Bin, ldb, C, Out, ldo,
-                                                        c.part[role], E, c.st, gate);
+      k_axpy_mf<PP / 16, GM, NORM><<<c.G, NT, 0, c.s>>>(c.n, c.p, Ain, lda, Bin, ldb, C, -1.0, Out,
+                                                        ldo, c.part[role], E, c.st, gate);
     } else {
       k_axpy<T, A, PP, GM, NORM><<<c.G, NT, 0, c.s>>>(c.n, c.p, Ain, lda, Bin, ldb, C, Out, ldo,
                                                       c.part[role], E, c.st, gate);
@@ -275,8 +275,12 @@ static void launch_update(Ctx& c, cx<T>* X, int ldx, cx<T>* S, int lds, const cx
     constexpr int PP = decltype(ppc)::value;
     double* part = WITH_U ? c.part[role] : nullptr;
     if constexpr (use_mfma<T>(PP)) {
-      k_update_mf<PP / 16, WITH_U><<<c.G, NT, 0, c.s>>>(c.n, c.p, X, ldx, S, lds, Q, ldq, U, ldu, V,
-                                                        ldv, C1, C2, part, E, c.st, gate);
+      // U = V + U C2 with U^T U, then X += S C1, S = Q + S C2: two launches
+      // over disjoint data keep each kernel within two waves' registers
+      if (WITH_U)
+        k_axpy_mf<PP / 16, G_UNCONJ, false><<<c.G, NT, 0, c.s>>>(c.n, c.p, V, ldv, U, ldu, C2, 1.0, U,
+                                                                 ldu, part, E, c.st, gate);
+      k_update_mf<PP / 16><<<c.G, NT, 0, c.s>>>(c.n, c.p, X, ldx, S, lds, Q, ldq, C1, C2, c.st, gate);
     } else {
       k_update<T, A, PP, WITH_U><<<c.G, NT, 0, c.s>>>(c.n, c.p, X, ldx, S, lds, Q, ldq, U, ldu, V,
                                                       ldv, C1, C2, part, E, c.st, gate);

@@ -11,10 +11,31 @@
 // neighbour), and ||Y||_F^2.
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
 #include "rowpass.hpp"
+#include "rowpass_mfma.hpp"
 
 namespace blk {
+
+// Gram Z^T Y of a 16-row x 32-column group staged in LDS (row-major,
+// ld 32), on the FP64 matrix cores: wave w accumulates the 16 x 16 block
+// (w / 2, w % 2) over four 4-row k-steps.
+__device__ inline void spmm_gram16(const z64* zs, const z64* ys, d4& gr, d4& gi) {
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int ib = w >> 1, jb = w & 1;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int r = 4 * s + (l >> 4);
+    const z64 a = zs[r * 32 + 16 * ib + (l & 15)];
+    const z64 b = ys[r * 32 + 16 * jb + (l & 15)];
+    gr = mfma64(a.re, b.re, gr);
+    gr = mfma64(-a.im, b.im, gr);
+    gi = mfma64(a.re, b.im, gi);
+    gi = mfma64(a.im, b.re, gi);
+  }
+}
 
 template <typename T, int PP, bool SUB, bool STORE, bool GRAM, bool NORM>
 __global__ __launch_bounds__(NT) void k_spmm(int64_t n, const int32_t* __restrict__ rowptr,
@@ -26,11 +47,15 @@ __global__ __launch_bounds__(NT) void k_spmm(int64_t n, const int32_t* __restric
                                              int E, const DevState* st, int gate, int remap) {
   if (st && gate >= st->stop_iter) return;
   constexpr int RPB = NT / PP;
-  __shared__ cx<T> zs[GRAM ? NT : 1];
-  __shared__ cx<T> ys[GRAM ? NT : 1];
+  // complex128 at p <= 32: the Gram runs on the matrix cores over 16-row groups
+  constexpr bool MFG = GRAM && std::is_same<T, double>::value && PP == 32;
+  __shared__ cx<T> zs[GRAM ? (MFG ? 2 * NT : NT) : 1];
+  __shared__ cx<T> ys[GRAM ? (MFG ? 2 * NT : NT) : 1];
   __shared__ double sh[NT / 64];
   GramAcc<T, double, PP, false> g;
-  if (GRAM) g.zero();
+  if (GRAM && !MFG) g.zero();
+  d4 mgr = d4{0.0, 0.0, 0.0, 0.0}, mgi = d4{0.0, 0.0, 0.0, 0.0};
+  int half = 0;
   double nrm = 0.0;
   const int lr = threadIdx.x / PP, c = threadIdx.x % PP;
   const bool cok = c < p;
@@ -71,7 +96,17 @@ __global__ __launch_bounds__(NT) void k_spmm(int64_t n, const int32_t* __restric
       if (GRAM && cok) zr = Z[row * ldz + c];
     }
     if (NORM) nrm += (double)cabs2(y);
-    if (GRAM) {
+    if constexpr (MFG) {
+      // rows of this tile fill half of the 16-row group (half is block-uniform)
+      zs[half * NT + threadIdx.x] = zr;
+      ys[half * NT + threadIdx.x] = y;
+      half ^= 1;
+      if (half == 0) {
+        __syncthreads();
+        spmm_gram16(reinterpret_cast<const z64*>(zs), reinterpret_cast<const z64*>(ys), mgr, mgi);
+        __syncthreads();
+      }
+    } else if (GRAM) {
       __syncthreads();
       zs[threadIdx.x] = zr;
       ys[threadIdx.x] = y;
@@ -79,9 +114,31 @@ __global__ __launch_bounds__(NT) void k_spmm(int64_t n, const int32_t* __restric
       g.add(zs, ys);
     }
   }
+  if constexpr (MFG) {
+    if (half == 1) {  // an odd tile count: the group's second half is zero
+      zs[NT + threadIdx.x] = czero<T>();
+      ys[NT + threadIdx.x] = czero<T>();
+      __syncthreads();
+      spmm_gram16(reinterpret_cast<const z64*>(zs), reinterpret_cast<const z64*>(ys), mgr, mgi);
+    }
+  }
   if (GRAM || NORM) {
     double* dst = part + (size_t)blockIdx.x * E;
-    if (GRAM) g.store(dst, p);
+    if constexpr (MFG) {
+      // D layout: register v of lane l holds G[16 ib + 4 v + l / 16][16 jb + l % 16]
+      const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+      const int j = 16 * (w & 1) + (l & 15);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * (w >> 1) + 4 * v + (l >> 4);
+        if (i < p && j < p) {
+          dst[2 * (i * p + j)] = mgr[v];
+          dst[2 * (i * p + j) + 1] = mgi[v];
+        }
+      }
+    } else if (GRAM) {
+      g.store(dst, p);
+    }
     if (NORM) {
       const double s = block_sum(nrm, sh);
       if (threadIdx.x == 0) dst[E - 1] = s;
