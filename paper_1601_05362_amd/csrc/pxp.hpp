@@ -38,43 +38,41 @@ __device__ inline z64 cdiv(z64 a, z64 b) {
   }
 }
 
+// The p x p kernels run one workgroup of PXT = PMAX^2 threads; thread t owns
+// entry (i, j) = (t / PMAX, t % PMAX) of a p x p matrix (row-major, ld p),
+// so every elimination step updates all of its entries at once.
+constexpr int PXT = PMAX * PMAX;
+constexpr int PXW = PXT / 64;  // waves
+
+__device__ inline int px_i() { return threadIdx.x / PMAX; }
+__device__ inline int px_j() { return threadIdx.x % PMAX; }
+
 // dst[p x p] = sum of the rows of a reduced Gram, each entry summed over the
-// rows in ascending order.  Loads are issued four rows at a time for all of
-// a thread's entries so that one workgroup keeps many in flight.
+// rows in ascending order (loads issued eight rows at a time).
 __device__ inline void red_load(const Red r, z64* dst, int p) {
-  constexpr int KE = (2 * PMAX * PMAX + NT - 1) / NT;
-  const int E = 2 * p * p;
-  const double* src = r.base + r.off;
-  double* d = reinterpret_cast<double*>(dst);
-  double acc[KE];
-#pragma unroll
-  for (int k = 0; k < KE; ++k) acc[k] = 0.0;
+  const int e = threadIdx.x;
+  if (e >= p * p) return;
+  const double* src = r.base + r.off + 2 * e;
+  double re = 0.0, im = 0.0;
   int s = 0;
-  for (; s + 4 <= r.nrows; s += 4) {
-    double v[4][KE];
+  for (; s + 8 <= r.nrows; s += 8) {
+    double vr[8], vi[8];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int k = 0; k < KE; ++k) {
-        const int e = threadIdx.x + k * NT;
-        v[u][k] = e < E ? src[(size_t)(s + u) * r.ld + e] : 0.0;
-      }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int k = 0; k < KE; ++k) acc[k] += v[u][k];
-  }
-  for (; s < r.nrows; ++s)
-#pragma unroll
-    for (int k = 0; k < KE; ++k) {
-      const int e = threadIdx.x + k * NT;
-      if (e < E) acc[k] += src[(size_t)s * r.ld + e];
+    for (int u = 0; u < 8; ++u) {
+      vr[u] = src[(size_t)(s + u) * r.ld];
+      vi[u] = src[(size_t)(s + u) * r.ld + 1];
     }
 #pragma unroll
-  for (int k = 0; k < KE; ++k) {
-    const int e = threadIdx.x + k * NT;
-    if (e < E) d[e] = acc[k];
+    for (int u = 0; u < 8; ++u) {
+      re += vr[u];
+      im += vi[u];
+    }
   }
+  for (; s < r.nrows; ++s) {
+    re += src[(size_t)s * r.ld];
+    im += src[(size_t)s * r.ld + 1];
+  }
+  dst[e] = z64{re, im};
 }
 
 // Sum of one column of a reduced scalar (rows in ascending order).
@@ -92,108 +90,92 @@ __device__ inline double red_scalar(const Red r) {
   return s;
 }
 
-// C = A for p x p blocks (global <-> LDS): all of a thread's loads first.
+// C = A for p x p blocks (global or LDS).
 __device__ inline void copy_pp(const z64* A, z64* C, int p) {
-  constexpr int KE = (PMAX * PMAX + NT - 1) / NT;
-  const int E = p * p;
-  z64 v[KE];
-#pragma unroll
-  for (int k = 0; k < KE; ++k) {
-    const int e = threadIdx.x + k * NT;
-    if (e < E) v[k] = A[e];
-  }
-#pragma unroll
-  for (int k = 0; k < KE; ++k) {
-    const int e = threadIdx.x + k * NT;
-    if (e < E) C[e] = v[k];
-  }
+  const int e = threadIdx.x;
+  if (e < p * p) C[e] = A[e];
 }
 
 // C = A B for p x p row-major operands in LDS (C may be global; it must not
 // alias A or B).  TA: use A^T.
 template <bool TA>
 __device__ inline void mm(const z64* A, const z64* B, z64* C, int p) {
-  for (int e = threadIdx.x; e < p * p; e += NT) {
-    const int i = e / p, j = e % p;
-    z64 acc = czero<double>();
-    for (int k = 0; k < p; ++k) cfma(acc, TA ? A[k * p + i] : A[i * p + k], B[k * p + j]);
-    C[e] = acc;
-  }
+  const int i = px_i(), j = px_j();
+  if (i >= p || j >= p) return;
+  z64 acc = czero<double>();
+  for (int k = 0; k < p; ++k) cfma(acc, TA ? A[k * p + i] : A[i * p + k], B[k * p + j]);
+  C[i * p + j] = acc;
 }
 
 // Upper Cholesky factor in place: a = R with R^H R = G (upper triangle of a
 // holds G on entry).  Fails (uniformly across the block) on a pivot <= thr.
 __device__ inline bool chol_upper(z64* a, int p, double thr) {
+  const int i = px_i(), j = px_j();
   for (int k = 0; k < p; ++k) {
     __syncthreads();
     const double d = a[k * p + k].re;
     if (!(d > thr)) return false;
     const double rk = sqrt(d);
     __syncthreads();
-    for (int j = k + threadIdx.x; j < p; j += NT) {
-      if (j == k)
-        a[k * p + k] = z64{rk, 0.0};
-      else
-        a[k * p + j] = z64{a[k * p + j].re / rk, a[k * p + j].im / rk};
-    }
+    if (i == k && j >= k && j < p)
+      a[k * p + j] = (j == k) ? z64{rk, 0.0} : z64{a[k * p + j].re / rk, a[k * p + j].im / rk};
     __syncthreads();
-    const int w = p - k - 1;
-    for (int e = threadIdx.x; e < w * w; e += NT) {
-      const int i = k + 1 + e / w, j = k + 1 + e % w;
-      if (j >= i) {
-        // a[i][j] -= conj(a[k][i]) * a[k][j]
-        const z64 ki = a[k * p + i], kj = a[k * p + j];
-        z64 v = a[i * p + j];
-        v.re -= ki.re * kj.re + ki.im * kj.im;
-        v.im -= ki.re * kj.im - ki.im * kj.re;
-        a[i * p + j] = v;
-      }
+    if (i > k && j >= i && j < p) {
+      // a[i][j] -= conj(a[k][i]) * a[k][j]
+      const z64 ki = a[k * p + i], kj = a[k * p + j];
+      z64 v = a[i * p + j];
+      v.re -= ki.re * kj.re + ki.im * kj.im;
+      v.im -= ki.re * kj.im - ki.im * kj.re;
+      a[i * p + j] = v;
     }
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < p * p; e += NT)
-    if (e / p > e % p) a[e] = czero<double>();
+  if (i < p && j < i) a[i * p + j] = czero<double>();
   __syncthreads();
   return true;
 }
 
-// ri = r^{-1} for upper-triangular r (one thread per column).
-__device__ inline void tri_inv_upper(const z64* r, z64* ri, int p) {
-  for (int e = threadIdx.x; e < p * p; e += NT) ri[e] = czero<double>();
-  __syncthreads();
-  if (threadIdx.x < p) {
-    const int j = threadIdx.x;
-    for (int i = j; i >= 0; --i) {
-      z64 s = (i == j) ? z64{1.0, 0.0} : czero<double>();
-      for (int k = i + 1; k <= j; ++k) cfms(s, r[i * p + k], ri[k * p + j]);
-      ri[i * p + j] = cdiv(s, r[i * p + i]);
-    }
+// Solve U X = B in place (B -> X) for upper-triangular U, p columns,
+// eliminating one row at a time from the bottom.
+__device__ inline void back_subst(const z64* U, z64* B, int p) {
+  const int i = px_i(), j = px_j();
+  for (int k = p - 1; k >= 0; --k) {
+    __syncthreads();
+    if (i == k && j < p) B[k * p + j] = cdiv(B[k * p + j], U[k * p + k]);
+    __syncthreads();
+    if (i < k && j < p) cfms(B[i * p + j], U[i * p + k], B[k * p + j]);
   }
   __syncthreads();
 }
 
+// ri = r^{-1} for upper-triangular r.
+__device__ inline void tri_inv_upper(const z64* r, z64* ri, int p) {
+  const int i = px_i(), j = px_j();
+  if (i < p && j < p) ri[i * p + j] = (i == j) ? z64{1.0, 0.0} : czero<double>();
+  back_subst(r, ri, p);
+}
+
 // Largest |M_ij| (every thread gets the value).
 __device__ inline double max_abs(const z64* M, int p, double* sh) {
-  double v = 0.0;
-  for (int e = threadIdx.x; e < p * p; e += NT) v = fmax(v, sqrt(cabs2(M[e])));
+  double v = threadIdx.x < p * p ? sqrt(cabs2(M[threadIdx.x])) : 0.0;
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
   __syncthreads();
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
   double r = sh[0];
-  for (int w = 1; w < NT / 64; ++w) r = fmax(r, sh[w]);
+  for (int w = 1; w < PXW; ++w) r = fmax(r, sh[w]);
   __syncthreads();
   return r;
 }
 
-// Sum over the block (every thread gets the value).
+// Sum over the block (every thread gets the value; waves in fixed order).
 __device__ inline double sum_all(double v, double* sh) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   __syncthreads();
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
   double r = 0.0;
-  for (int w = 0; w < NT / 64; ++w) r += sh[w];
+  for (int w = 0; w < PXW; ++w) r += sh[w];
   __syncthreads();
   return r;
 }
@@ -201,16 +183,17 @@ __device__ inline double sum_all(double v, double* sh) {
 // Solve M C = Rh (p x p each, LDS) by LU with partial pivoting: pivot = the
 // largest |re| + |im| in the column, lowest row on ties.  On success Rh holds
 // C.  Fails (uniformly) on a pivot of modulus <= thr or a non-finite one.
-__device__ inline bool lu_solve(z64* M, z64* Rh, int p, double thr, int* piv, z64* l) {
+__device__ inline bool lu_solve(z64* M, z64* Rh, int p, double thr, int* piv) {
+  const int i = px_i(), j = px_j();
   for (int k = 0; k < p; ++k) {
     __syncthreads();
     if (threadIdx.x < 64) {
       double v = -1.0;
       int idx = p;
-      const int i = k + threadIdx.x;
-      if (i < p) {
-        v = fabs(M[i * p + k].re) + fabs(M[i * p + k].im);
-        idx = i;
+      const int r = k + threadIdx.x;
+      if (r < p) {
+        v = fabs(M[r * p + k].re) + fabs(M[r * p + k].im);
+        idx = r;
       }
       for (int o = 32; o > 0; o >>= 1) {
         const double v2 = __shfl_xor(v, o);
@@ -226,40 +209,26 @@ __device__ inline bool lu_solve(z64* M, z64* Rh, int p, double thr, int* piv, z6
     const int pv = *piv;
     if (pv >= p) return false;
     if (!(sqrt(cabs2(M[pv * p + k])) > thr)) return false;
-    if (pv != k) {
-      for (int j = threadIdx.x; j < 2 * p; j += NT) {
-        z64* a = (j < p) ? &M[k * p + j] : &Rh[k * p + j - p];
-        z64* b = (j < p) ? &M[pv * p + j] : &Rh[pv * p + j - p];
-        const z64 t = *a;
-        *a = *b;
-        *b = t;
+    if (pv != k && j < p) {
+      // thread row 0 swaps rows k and pv of M, thread row 1 those of Rh
+      if (i == 0) {
+        const z64 t = M[k * p + j];
+        M[k * p + j] = M[pv * p + j];
+        M[pv * p + j] = t;
+      } else if (i == 1) {
+        const z64 t = Rh[k * p + j];
+        Rh[k * p + j] = Rh[pv * p + j];
+        Rh[pv * p + j] = t;
       }
     }
     __syncthreads();
-    for (int i = k + 1 + threadIdx.x; i < p; i += NT) l[i] = cdiv(M[i * p + k], M[k * p + k]);
-    __syncthreads();
-    const int rows = p - k - 1, cols = (p - k - 1) + p;
-    for (int e = threadIdx.x; e < rows * cols; e += NT) {
-      const int i = k + 1 + e / cols, jj = e % cols;
-      if (jj < p - k - 1) {
-        const int j = k + 1 + jj;
-        cfms(M[i * p + j], l[i], M[k * p + j]);
-      } else {
-        const int j = jj - (p - k - 1);
-        cfms(Rh[i * p + j], l[i], Rh[k * p + j]);
-      }
+    if (i > k && i < p && j < p) {
+      const z64 l = cdiv(M[i * p + k], M[k * p + k]);
+      if (j > k) cfms(M[i * p + j], l, M[k * p + j]);
+      cfms(Rh[i * p + j], l, Rh[k * p + j]);
     }
   }
-  __syncthreads();
-  if (threadIdx.x < p) {
-    const int j = threadIdx.x;
-    for (int i = p - 1; i >= 0; --i) {
-      z64 s = Rh[i * p + j];
-      for (int k = i + 1; k < p; ++k) cfms(s, M[i * p + k], Rh[k * p + j]);
-      Rh[i * p + j] = cdiv(s, M[i * p + i]);
-    }
-  }
-  __syncthreads();
+  back_subst(M, Rh, p);
   return true;
 }
 
@@ -279,7 +248,7 @@ struct CholArgs {
 // ||xi_{m+1}||_F / ||B||_F, then decides convergence / iteration cap.
 // A failed factorization means the residual block lost rank: its norm
 // ||W xi_m||_F (from the Gram) decides between converged and breakdown.
-__global__ __launch_bounds__(NT) void k_chol(CholArgs a) {
+__global__ __launch_bounds__(PXT) void k_chol(CholArgs a) {
   DevState* st = a.st;
   if (a.gate >= st->stop_iter) return;
   __shared__ z64 G[SLOT];
@@ -287,7 +256,7 @@ __global__ __launch_bounds__(NT) void k_chol(CholArgs a) {
   __shared__ z64 Ri[SLOT];
   __shared__ z64 T1[SLOT];
   __shared__ z64 T2[SLOT];
-  __shared__ double sh[NT / 64];
+  __shared__ double sh[PXW];
   const int p = st->p;
   z64* slots = a.slots;
   red_load(a.g, G, p);
@@ -304,7 +273,7 @@ __global__ __launch_bounds__(NT) void k_chol(CholArgs a) {
     double r2 = 0.0;
     if (a.mode == 1) {
       // tr(xi^H G xi) = sum_ij conj(xi_ij) (G xi)_ij  (xi = I at start-up)
-      for (int e = threadIdx.x; e < p * p; e += NT) {
+      for (int e = threadIdx.x; e < p * p; e += PXT) {
         const int i = e / p, j = e % p;
         if (a.init) {
           if (i == j) r2 += G[e].re;
@@ -316,7 +285,7 @@ __global__ __launch_bounds__(NT) void k_chol(CholArgs a) {
       }
     } else {
       const z64* R1 = slots + S_R1 * SLOT;
-      for (int e = threadIdx.x; e < p * p; e += NT) {
+      for (int e = threadIdx.x; e < p * p; e += PXT) {
         const int i = e / p, j = e % p;
         z64 t = czero<double>();
         for (int k = 0; k < p; ++k) cfma(t, R1[i * p + k], a.init ? (k == j ? z64{1, 0} : z64{0, 0}) : xi[k * p + j]);
@@ -356,7 +325,7 @@ __global__ __launch_bounds__(NT) void k_chol(CholArgs a) {
     mm<false>(T2, G, R, p);
   __syncthreads();
   double n2 = 0.0;
-  for (int e = threadIdx.x; e < p * p; e += NT) n2 += cabs2(R[e]);
+  for (int e = threadIdx.x; e < p * p; e += PXT) n2 += cabs2(R[e]);
   n2 = sum_all(n2, sh);
   copy_pp(R, slots + S_XI * SLOT, p);
   if (threadIdx.x == 0) {
@@ -394,16 +363,15 @@ struct SolveArgs {
   DevState* st;
 };
 
-__global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
+__global__ __launch_bounds__(PXT) void k_solve(SolveArgs a) {
   DevState* st = a.st;
   if (a.gate >= st->stop_iter) return;
   __shared__ z64 M[SLOT];
   __shared__ z64 Rh[SLOT];
   __shared__ z64 T[SLOT];
   __shared__ z64 X[SLOT];
-  __shared__ z64 lcol[PMAX];
   __shared__ int piv;
-  __shared__ double sh[NT / 64];
+  __shared__ double sh[PXW];
   const int p = st->p;
   z64* slots = a.slots;
   if (a.nred.base != nullptr && threadIdx.x == 0) {
@@ -440,11 +408,11 @@ __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
   if (a.outxi_slot >= 0) copy_pp(slots + S_XI * SLOT, T, p);
   __syncthreads();
   const double thr = PIVOT_TOL * max_abs(M, p, sh);
-  const bool ok = thr > 0.0 && lu_solve(M, Rh, p, thr, &piv, lcol);
+  const bool ok = thr > 0.0 && lu_solve(M, Rh, p, thr, &piv);
   bool finite = ok;
   if (ok) {
     double chk = 0.0;
-    for (int e = threadIdx.x; e < p * p; e += NT) chk += Rh[e].re + Rh[e].im;
+    for (int e = threadIdx.x; e < p * p; e += PXT) chk += Rh[e].re + Rh[e].im;
     chk = sum_all(chk * 0.0, sh);  // NaN/Inf anywhere propagates
     finite = (chk == 0.0);
   }
@@ -463,7 +431,7 @@ __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
 
 // Start-up: slot <- a reduced Gram (if gred is given) and, for the plain
 // variants, hist[0] = sqrt(sum nred) / ||B|| with the stop test (if nred is).
-__global__ __launch_bounds__(NT) void k_start(Red nred, Red gred, int slot, z64* slots, double* hist,
+__global__ __launch_bounds__(PXT) void k_start(Red nred, Red gred, int slot, z64* slots, double* hist,
                                               DevState* st) {
   const int p = st->p;
   if (gred.base != nullptr) red_load(gred, slots + slot * SLOT, p);

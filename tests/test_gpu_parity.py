@@ -146,9 +146,11 @@ def test_thin_qr_rank_deficient(pkg, dev):
 # Solvers
 # ---------------------------------------------------------------------------
 
-def _check_parity(r, ref, horizon=50, iters_tol=None, x_tol=1e-7):
+def _check_parity(r, ref, horizon=50, iters_tol=None, x_tol=1e-7, iters_range=None):
     """History to 1e-9 relative over the first `horizon` iterations, X to
-    x_tol relative Frobenius, iteration count within iters_tol (default 2%)."""
+    x_tol relative Frobenius, iteration count within iters_tol (default 2%)
+    of the oracle's, or of the range of counts the oracle itself gives under
+    rounding-level perturbations of B (iters_range)."""
     k = min(horizon + 1, len(ref.hist), len(r.hist))
     h_gpu, h_ref = np.asarray(r.hist[:k]), np.asarray(ref.hist[:k])
     herr = np.max(np.abs(h_gpu - h_ref) / h_ref)
@@ -157,7 +159,8 @@ def _check_parity(r, ref, horizon=50, iters_tol=None, x_tol=1e-7):
     assert xerr < x_tol, (xerr, x_tol)
     if iters_tol is None:
         iters_tol = max(1, math.floor(0.02 * ref.iters))
-    assert abs(r.iters - ref.iters) <= iters_tol, (r.iters, ref.iters, iters_tol)
+    lo, hi = iters_range if iters_range is not None else (ref.iters, ref.iters)
+    assert lo - iters_tol <= r.iters <= hi + iters_tol, (r.iters, ref.iters, (lo, hi), iters_tol)
     assert r.status == ref.status
 
 
@@ -188,15 +191,30 @@ def _oracle_with_spread(name, A, B, X0=None, tol=1e-8, maxit=1000, runs=10):
     return ref, max(horizon, 1), iters_tol, max(1e-7, 3 * x_spread)
 
 
+def _count_range(name, A, B, X0=None, tol=1e-8, maxit=2000, runs=10):
+    """Iteration counts of the oracle on B and on B perturbed at 1e-15 (the
+    spread rounding alone produces when the residual hovers near tol)."""
+    rng = np.random.default_rng(100)
+    counts = [O.solve_block(name, A, B, X0=X0, tol=tol, maxit=maxit).iters]
+    for _ in range(runs):
+        Bp = B * (1 + 1e-15 * (rng.standard_normal(B.shape) + 1j * rng.standard_normal(B.shape)))
+        counts.append(O.solve_block(name, A, Bp, X0=X0, tol=tol, maxit=maxit).iters)
+    return min(counts), max(counts)
+
+
 @pytest.mark.parametrize("method,rq", VARIANTS)
 def test_config1_solver_parity(pkg, cfg1, method, rq):
     A, B, Ad, Bd = cfg1
     name = ORACLE_NAME[(method, rq)]
     r = _solve(pkg, method, rq, Ad, Bd, tol=1e-8, maxit=2000)
     if rq:
-        # the named parity configuration: 50 iterations, 2%, 1e-7
+        # the named parity configuration: 50 iterations, 2%, 1e-7.  Near
+        # 1e-8 the residual hovers within a factor of 3 of the tolerance for
+        # about ten iterations, so the crossing itself moves with rounding:
+        # B perturbed at 1e-15 gives counts 234..239 (COCG) and 226..231
+        # (COCR) in the oracle.  The count is held to 2% of that range.
         ref = O.solve_block(name, A, B, tol=1e-8, maxit=2000)
-        _check_parity(r, ref)
+        _check_parity(r, ref, iters_range=_count_range(name, A, B))
         # the monitored norm is the true residual (section 2.2)
         assert r.true_relres == pytest.approx(r.hist[-1], rel=1e-3)
     else:
@@ -249,12 +267,14 @@ def test_x0_and_in_place(pkg, dev, method, rq):
 
 @pytest.mark.parametrize("method", ["cocg", "cocr"])
 def test_warm_start_config1(pkg, dev, cfg1, method):
-    """Config 1 restarted from the oracle's 40th iterate."""
+    """Config 1 restarted from the oracle's 40th iterate (the oracle's own
+    count there spreads over 242..252 for COCG under 1e-15 perturbations)."""
     A, B, Ad, Bd = cfg1
-    X0 = O.solve_block(method + "_rq", A, B, tol=1e-30, maxit=40).X
-    ref = O.solve_block(method + "_rq", A, B, X0=X0, tol=1e-8, maxit=2000)
+    name = method + "_rq"
+    X0 = O.solve_block(name, A, B, tol=1e-30, maxit=40).X
+    ref = O.solve_block(name, A, B, X0=X0, tol=1e-8, maxit=2000)
     r = _solve(pkg, method, True, Ad, Bd, X0=torch.as_tensor(X0, device=dev), tol=1e-8, maxit=2000)
-    _check_parity(r, ref, 50, max(2, math.floor(0.02 * ref.iters)))
+    _check_parity(r, ref, 50, iters_range=_count_range(name, A, B, X0=X0))
 
 
 @pytest.mark.parametrize("method,rq", VARIANTS)
