@@ -46,14 +46,31 @@ typedef struct { float re, im; } blk_c;  /* complex64 */
 /* Operator kinds. */
 enum { BLK_OP_CSR = 0, BLK_OP_DENSE = 1 };
 
+/* Pattern knowledge of a CSR operator (blk_op.structure). */
+enum {
+  BLK_STRUCT_UNKNOWN = 0, /* the solvers analyse the pattern once per call
+                             (blk_op_analyze); single products use the
+                             general CSR kernel */
+  BLK_STRUCT_GENERAL = 1, /* never analyse: always the general CSR kernel */
+  BLK_STRUCT_GRID = 2     /* the pattern is the 7-point stencil of the
+                             lexicographic grid[0] x grid[1] x grid[2] grid
+                             (x fastest; 5-point when grid[2] == 1), columns
+                             ascending within each row.  Set by
+                             blk_op_analyze after checking every row; a
+                             caller that sets it guarantees the pattern. */
+};
+
 /* The matrix A of eq. (1.1).  Symmetry (A = A^T) is the caller's promise and
  * is not checked on the device.
  *   CSR:   0-based int32 rowptr[n+1], colind[nnz], complex128 val[nnz];
  *          column indices need not be sorted; a row may be empty.
- *   DENSE: row-major complex128 `dense` with leading dimension ld >= n. */
+ *   DENSE: row-major complex128 `dense` with leading dimension ld >= n.
+ * structure / grid: see BLK_STRUCT_*; ignored for DENSE.  With
+ * BLK_STRUCT_GRID the CSR values are still read (any coefficients); the
+ * column indices are not. */
 typedef struct {
   int32_t kind;
-  int32_t reserved;
+  int32_t structure;
   int64_t n;
   int64_t nnz;
   const int32_t *rowptr;
@@ -61,6 +78,7 @@ typedef struct {
   const blk_z *val;
   const blk_z *dense;
   int64_t ld;
+  int64_t grid[3];
 } blk_op;
 
 /* Arithmetic of a solve. */
@@ -154,6 +172,17 @@ int32_t blk_cocr_solve(const blk_op *A, int64_t p, const blk_z *B, int64_t ldb, 
  */
 int32_t blk_spmm_z(const blk_op *A, int64_t p, const blk_z *Z, int64_t ldz, const blk_z *C,
                    int64_t ldc, blk_z *Y, int64_t ldy, blk_z *gram, void *stream);
+
+/*
+ * Pattern analysis of A (section 3's operators are grid stencils): sets
+ * A->structure to BLK_STRUCT_GRID and A->grid to (nx, ny, nz) when every row
+ * of the CSR pattern is that of the 7-point (nz > 1) or 5-point (nz == 1)
+ * stencil of a lexicographic grid with nx, ny >= 2, else to
+ * BLK_STRUCT_GENERAL (always for DENSE).  Reads rowptr and colind once on
+ * the device; host-blocking; allocates a 4-byte flag.  The result stays
+ * valid while the pattern (not the values) is unchanged.
+ */
+int32_t blk_op_analyze(blk_op *A, void *stream);
 
 /*
  * The same product in complex64 for a CSR operator whose values are given in

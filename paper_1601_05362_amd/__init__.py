@@ -38,6 +38,7 @@ __all__ = [
     "SolveResult",
     "blk_cocg_solve",
     "blk_cocr_solve",
+    "blk_op_analyze",
     "blk_spmm_z",
     "blk_spmm_c",
     "blk_gram_z",
@@ -101,6 +102,8 @@ class CsrOperator:
         self.nnz = colind.numel()
         self.device = val.device
         self._val32 = None
+        self.structure = _capi.BLK_STRUCT_UNKNOWN
+        self.grid = (0, 0, 0)
 
     @classmethod
     def from_arrays(cls, rowptr, colind, val, device="cuda"):
@@ -117,9 +120,22 @@ class CsrOperator:
             self._val32 = self.val.to(torch.complex64)
         return self._val32
 
+    def analyze(self) -> "CsrOperator":
+        """Check the pattern once (blk_op_analyze); a grid-stencil pattern
+        then takes the 2.5D blocked product in every later call."""
+        op = self.as_c()
+        with torch.cuda.device(self.device):
+            rc = _lib().blk_op_analyze(C.byref(op), _stream(self.device))
+        if rc != 0:
+            _raise(rc, "blk_op_analyze")
+        self.structure = op.structure
+        self.grid = tuple(op.grid)
+        return self
+
     def as_c(self) -> _capi.BlkOp:
-        return _capi.BlkOp(BLK_OP_CSR, 0, self.n, self.nnz, self.rowptr.data_ptr(),
-                           self.colind.data_ptr(), self.val.data_ptr(), None, 0)
+        return _capi.BlkOp(BLK_OP_CSR, self.structure, self.n, self.nnz, self.rowptr.data_ptr(),
+                           self.colind.data_ptr(), self.val.data_ptr(), None, 0,
+                           (C.c_int64 * 3)(*self.grid))
 
 
 class DenseOperator:
@@ -135,8 +151,8 @@ class DenseOperator:
         self.device = a.device
 
     def as_c(self) -> _capi.BlkOp:
-        return _capi.BlkOp(BLK_OP_DENSE, 0, self.n, 0, None, None, None, self.a.data_ptr(),
-                           self.a.stride(0))
+        return _capi.BlkOp(BLK_OP_DENSE, _capi.BLK_STRUCT_GENERAL, self.n, 0, None, None, None,
+                           self.a.data_ptr(), self.a.stride(0), (C.c_int64 * 3)(0, 0, 0))
 
 
 @dataclass
@@ -198,6 +214,14 @@ def blk_cocr_solve(A, B, X0=None, tol=1e-8, maxit=1000, *, rq=True, precision="f
     orthonormalization (rq=True, Algorithm 3) for A X = B."""
     return _solve("blk_cocr_solve", A, B, X0, tol, maxit, rq, precision, inner_tol,
                   inner_maxit, check_every, out, refine)
+
+
+def blk_op_analyze(A):
+    """Pattern analysis of a CSR operator (grid-stencil detection); returns A
+    with its `structure` and `grid` set.  Dense operators need none."""
+    if isinstance(A, CsrOperator):
+        return A.analyze()
+    return A
 
 
 def blk_spmm_z(A, Z: torch.Tensor, C_: torch.Tensor | None = None, out=None, gram=False):

@@ -24,10 +24,13 @@ STATUS_NAMES = {
 }
 
 
+BLK_STRUCT_UNKNOWN, BLK_STRUCT_GENERAL, BLK_STRUCT_GRID = 0, 1, 2
+
+
 class BlkOp(C.Structure):
     _fields_ = [
         ("kind", C.c_int32),
-        ("reserved", C.c_int32),
+        ("structure", C.c_int32),
         ("n", C.c_int64),
         ("nnz", C.c_int64),
         ("rowptr", C.c_void_p),
@@ -35,6 +38,7 @@ class BlkOp(C.Structure):
         ("val", C.c_void_p),
         ("dense", C.c_void_p),
         ("ld", C.c_int64),
+        ("grid", C.c_int64 * 3),
     ]
 
 
@@ -64,6 +68,7 @@ SIGNATURES = {
     "blk_cocr_solve": (_I32, [C.POINTER(BlkOp), _I64, _P, _I64, _P, _I64, _D, _I32,
                               C.POINTER(BlkOpts), _P, _I64, _DP, _IP, _DP]),
     "blk_spmm_z": (_I32, [C.POINTER(BlkOp), _I64, _P, _I64, _P, _I64, _P, _I64, _P, _P]),
+    "blk_op_analyze": (_I32, [C.POINTER(BlkOp), _P]),
     "blk_spmm_c": (_I32, [_I64, _I64, _P, _P, _P, _I64, _P, _I64, _P, _I64, _P]),
     "blk_gram_z": (_I32, [_I64, _I64, _P, _I64, _P, _I64, _I32, _P, _P]),
     "blk_thin_qr_z": (_I32, [_I64, _I64, _P, _I64, _P, _I64, _P, _P]),

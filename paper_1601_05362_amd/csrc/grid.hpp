@@ -1,0 +1,211 @@
+// Operator application Y = A Z for a CSR matrix whose pattern is the
+// 7-point stencil of a lexicographic nx x ny x nz grid (5-point when nz = 1):
+// row r = x + nx (y + ny z) holds, in ascending column order, the existing
+// ones of r - nx ny, r - nx, r - 1, r, r + 1, r + nx, r + nx ny.  The values
+// are read from the CSR (any coefficients); the column indices are not
+// read, since the pattern has been verified (k_grid_check).
+//
+// 2.5D blocking: a workgroup owns a GTX x GTY tile of an x-y plane and walks
+// GLZ consecutive planes.  Each of its 32 thread rows owns one grid point and
+// p = 32 lanes its columns.  The current plane plus a one-point halo sits in
+// LDS (the +-x, +-y neighbours); the -z and +z neighbours stay in registers
+// as the walk advances, so each Z row is fetched about once per plane
+// instead of once per stored entry.  The same fused epilogues as the CSR
+// kernel: Y = C - A Z, the Gram Z^T Y (FP64 matrix cores) and ||Y||_F^2.
+#pragma once
+
+#include "common.hpp"
+#include "rowpass_mfma.hpp"
+
+namespace blk {
+
+constexpr int GT = 1024;  // threads: 32 grid points x 32 columns
+constexpr int GTX = 8, GTY = 4, GLZ = 32;
+static_assert(GTX * GTY * 32 == GT, "one thread row per tile point");
+
+// Grid units of a launch: (x-y tile, z chunk) pairs.
+__host__ __device__ inline int64_t grid_units(int nx, int ny, int nz) {
+  return (int64_t)((nx + GTX - 1) / GTX) * ((ny + GTY - 1) / GTY) * ((nz + GLZ - 1) / GLZ);
+}
+
+// Verify the stencil pattern: any mismatching row stores 1 to *bad.
+__global__ __launch_bounds__(NT) void k_grid_check(int64_t n, const int32_t* __restrict__ rowptr,
+                                                   const int32_t* __restrict__ colind, int nx, int ny,
+                                                   int nz, int* bad) {
+  const int64_t r = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (r >= n) return;
+  const int64_t sxy = (int64_t)nx * ny;
+  const int x = (int)(r % nx), y = (int)((r / nx) % ny), z = (int)(r / sxy);
+  int64_t want[7];
+  int cnt = 0;
+  if (z > 0) want[cnt++] = r - sxy;
+  if (y > 0) want[cnt++] = r - nx;
+  if (x > 0) want[cnt++] = r - 1;
+  want[cnt++] = r;
+  if (x < nx - 1) want[cnt++] = r + 1;
+  if (y < ny - 1) want[cnt++] = r + nx;
+  if (z < nz - 1) want[cnt++] = r + sxy;
+  const int k0 = rowptr[r], k1 = rowptr[r + 1];
+  bool ok = (k1 - k0 == cnt);
+  for (int i = 0; ok && i < cnt; ++i) ok = (colind[k0 + i] == want[i]);
+  if (!ok) *bad = 1;
+}
+
+// Gram block (ib, jb) of a 16-row group staged in LDS (row-major, ld 32).
+__device__ inline void grid_gram16(const z64* zs, const z64* ys, int ib, int jb, d4& gr, d4& gi) {
+  const int l = threadIdx.x & 63;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int r = 4 * s + (l >> 4);
+    const z64 a = zs[r * 32 + 16 * ib + (l & 15)];
+    const z64 b = ys[r * 32 + 16 * jb + (l & 15)];
+    gr = mfma64(a.re, b.re, gr);
+    gr = mfma64(-a.im, b.im, gr);
+    gi = mfma64(a.re, b.im, gi);
+    gi = mfma64(a.im, b.re, gi);
+    // one k-step's operands at a time: batching the LDS reads of all steps
+    // would raise the kernel's register count and halve its occupancy
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+template <typename T, bool SUB, bool STORE, bool GRAM, bool NORM>
+__global__ __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(8))) void k_spmm_grid(int nx, int ny, int nz,
+                                                  const int32_t* __restrict__ rowptr,
+                                                  const cx<T>* __restrict__ val,
+                                                  const cx<T>* __restrict__ Z, int ldz,
+                                                  const cx<T>* __restrict__ Cm, int ldc,
+                                                  cx<T>* __restrict__ Y, int ldy, int p, double* part,
+                                                  int E, const DevState* st, int gate) {
+  if (st && gate >= st->stop_iter) return;
+  constexpr int W = GTX + 2, H = GTY + 2, NH = 2 * (GTX + GTY);
+  constexpr int PL = W * H * 32;  // plane + halo, in cx<T>
+  // with GRAM the plane buffer also stages the 32 Z and Y rows (as z64)
+  constexpr int PB = (int)sizeof(cx<T>) * PL, GB = GRAM ? 2 * 32 * 32 * 16 : 0;
+  __shared__ __align__(16) char lds_buf[PB > GB ? PB : GB];
+  // Gram accumulators of waves 0-3 (block (w >> 1, w & 1)) between planes,
+  // kept in LDS so that no registers stay live across the walk
+  __shared__ __align__(16) double gacc[GRAM ? 4 * 2 * 4 * 64 : 1];
+  __shared__ double sh[GT / 64];
+  cx<T>* pl = reinterpret_cast<cx<T>*>(lds_buf);
+  z64* gs = reinterpret_cast<z64*>(lds_buf);
+  const int c = threadIdx.x & 31, q = threadIdx.x >> 5, w = threadIdx.x >> 6;
+  const bool cok = c < p;
+  const int tilesx = (nx + GTX - 1) / GTX, tilesy = (ny + GTY - 1) / GTY;
+  const int64_t units = grid_units(nx, ny, nz);
+  const int64_t sxy = (int64_t)nx * ny;
+  // halo point owned by thread row q (q < NH): ring of the (W x H) frame
+  int hx = 0, hy = 0;
+  if (q < GTX) {
+    hx = q + 1;
+  } else if (q < 2 * GTX) {
+    hx = q - GTX + 1;
+    hy = H - 1;
+  } else if (q < 2 * GTX + GTY) {
+    hy = q - 2 * GTX + 1;
+  } else {
+    hx = W - 1;
+    hy = q - 2 * GTX - GTY + 1;
+  }
+  const int lx = q % GTX + 1, ly = q / GTX + 1;  // this point's frame position
+  const int l = threadIdx.x & 63;
+  if (GRAM && w < 4)
+    for (int k = 0; k < 8; ++k) gacc[(w * 8 + k) * 64 + l] = 0.0;
+  double nrm = 0.0;
+  for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
+    const int bx = (int)(u % tilesx), by = (int)((u / tilesx) % tilesy), bz = (int)(u / ((int64_t)tilesx * tilesy));
+    const int x = bx * GTX + q % GTX, y = by * GTY + q / GTX;
+    const int z0 = bz * GLZ, z1 = min(nz, z0 + GLZ);
+    const bool in = x < nx && y < ny;
+    const int64_t r0 = in ? x + (int64_t)nx * y : 0;
+    const int ex = bx * GTX + hx - 1, ey = by * GTY + hy - 1;
+    const bool hok = q < NH && ex >= 0 && ex < nx && ey >= 0 && ey < ny && cok;
+    const int64_t hr0 = hok ? ex + (int64_t)nx * ey : 0;
+    cx<T> prev = (in && cok && z0 > 0) ? Z[(r0 + sxy * (z0 - 1)) * ldz + c] : czero<T>();
+    cx<T> cur = (in && cok) ? Z[(r0 + sxy * z0) * ldz + c] : czero<T>();
+    for (int z = z0; z < z1; ++z) {
+      const int64_t r = r0 + sxy * z;
+      const cx<T> nxt = (in && cok && z + 1 < nz) ? Z[(r + sxy) * ldz + c] : czero<T>();
+      const int rp = in ? rowptr[r] : 0;
+      if (q < NH) pl[(hy * W + hx) * 32 + c] = hok ? Z[(hr0 + sxy * z) * ldz + c] : czero<T>();
+      pl[(ly * W + lx) * 32 + c] = cur;
+      __syncthreads();
+      cx<T> yv = czero<T>();
+      if (in) {
+        // CSR slots of the existing neighbours, in column order
+        const bool h0 = z > 0, h1 = y > 0, h2 = x > 0, h4 = x < nx - 1, h5 = y < ny - 1, h6 = z < nz - 1;
+        const int s1 = h0, s2 = s1 + h1, s3 = s2 + h2, s4 = s3 + 1, s5 = s4 + h4, s6 = s5 + h5;
+        const cx<T>* v = val + rp;
+        cx<T> acc = czero<T>();
+        if (h0) cfma(acc, v[0], prev);
+        if (h1) cfma(acc, v[s1], pl[((ly - 1) * W + lx) * 32 + c]);
+        if (h2) cfma(acc, v[s2], pl[(ly * W + lx - 1) * 32 + c]);
+        cfma(acc, v[s3], cur);
+        if (h4) cfma(acc, v[s4], pl[(ly * W + lx + 1) * 32 + c]);
+        if (h5) cfma(acc, v[s5], pl[((ly + 1) * W + lx) * 32 + c]);
+        if (h6) cfma(acc, v[s6], nxt);
+        if (cok) {
+          yv = SUB ? csub(Cm[r * ldc + c], acc) : acc;
+          if (STORE) Y[r * ldy + c] = yv;
+        }
+      }
+      if (NORM) nrm += (double)cabs2(yv);
+      if (GRAM) {
+        __syncthreads();  // the plane has been read; stage the rows over it
+        gs[q * 32 + c] = z64{(double)cur.re, (double)cur.im};
+        gs[32 * 32 + q * 32 + c] = z64{(double)yv.re, (double)yv.im};
+        __syncthreads();
+        if (w < 4) {
+          d4 gr, gi;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            gr[v] = gacc[(w * 8 + v) * 64 + l];
+            gi[v] = gacc[(w * 8 + 4 + v) * 64 + l];
+          }
+          // rows 0-15, then rows 16-31
+          grid_gram16(gs, gs + 32 * 32, (w >> 1) & 1, w & 1, gr, gi);
+          grid_gram16(gs + 16 * 32, gs + 32 * 32 + 16 * 32, (w >> 1) & 1, w & 1, gr, gi);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            gacc[(w * 8 + v) * 64 + l] = gr[v];
+            gacc[(w * 8 + 4 + v) * 64 + l] = gi[v];
+          }
+        }
+      }
+      __syncthreads();  // the buffer is free for the next plane
+      prev = cur;
+      cur = nxt;
+    }
+  }
+  if (GRAM || NORM) {
+    double* dst = part + (size_t)blockIdx.x * E;
+    if (GRAM) {
+      __syncthreads();
+      if (w < 4) {
+        const int ib = (w >> 1) & 1, jb = w & 1;
+        const int j = 16 * jb + (l & 15);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = 16 * ib + 4 * v + (l >> 4);
+          if (i < p && j < p) {
+            dst[2 * (i * p + j)] = gacc[(w * 8 + v) * 64 + l];
+            dst[2 * (i * p + j) + 1] = gacc[(w * 8 + 4 + v) * 64 + l];
+          }
+        }
+      }
+    }
+    if (NORM) {
+      for (int o = 32; o > 0; o >>= 1) nrm += __shfl_xor(nrm, o);
+      __syncthreads();
+      if ((threadIdx.x & 63) == 0) sh[w] = nrm;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int k = 0; k < GT / 64; ++k) s += sh[k];
+        dst[E - 1] = s;
+      }
+    }
+  }
+}
+
+}  // namespace blk

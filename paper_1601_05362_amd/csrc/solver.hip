@@ -32,6 +32,7 @@
 #include "pxp.hpp"
 #include "rowpass.hpp"
 #include "rowpass_mfma.hpp"
+#include "grid.hpp"
 #include "spmm.hpp"
 
 namespace blk {
@@ -181,6 +182,7 @@ struct DevOp {
   const cx<T>* val = nullptr;
   const cx<T>* dense = nullptr;
   int64_t ld = 0;
+  int gnx = 0, gny = 0, gnz = 0;  // gnx > 0: verified grid-stencil pattern
 };
 
 // Y = A Z (SUB: Y = C - A Z), optional store / Gram Z^T Y / ||Y||^2.
@@ -191,6 +193,19 @@ static void apply_op(Ctx& c, const DevOp<T>& A, const cx<T>* Z, int ldz, const c
     constexpr int PP = decltype(ppc)::value;
     double* part = (GRAM || NORM) ? c.part[role] : nullptr;
     const DevState* st = c.st;
+    if constexpr (PP == 32) {
+      if (A.kind == BLK_OP_CSR && A.gnx > 0) {
+        // grid-stencil pattern: 2.5D blocked product; with a reduction the
+        // grid is bounded by the partial buffers (blocks loop over units)
+        const int64_t units = grid_units(A.gnx, A.gny, A.gnz);
+        const int64_t G = (GRAM || NORM) ? std::min<int64_t>(units, std::max(c.G, c.Gs)) : units;
+        if (GRAM || NORM) c.nblk[role] = (int)G;
+        k_spmm_grid<T, SUB, STORE, GRAM, NORM><<<(unsigned)G, GT, 0, c.s>>>(
+            A.gnx, A.gny, A.gnz, A.rowptr, A.val, Z, ldz, C, ldc, Y, ldy, c.p, part, E, st, gate);
+        LAUNCH_CHECK();
+        return;
+      }
+    }
     if (A.kind == BLK_OP_CSR) {
       // Without a reduction every tile of RPB rows is its own block, which
       // keeps the most waves in flight; with one, the grid is bounded by
@@ -656,6 +671,9 @@ static SolveOut run_mixed(Ctx& c, Pool& pool, const blk_op* A, const DevOp<doubl
   A32.rowptr = A->rowptr;
   A32.colind = A->colind;
   A32.ld = A->kind == BLK_OP_DENSE ? n : 0;
+  A32.gnx = A64.gnx;
+  A32.gny = A64.gny;
+  A32.gnz = A64.gnz;
   k_state_init<<<1, 64, 0, c.s>>>(c.st, pi, maxit, tol, INFINITY);
   LAUNCH_CHECK();
   if (A->kind == BLK_OP_CSR) {
@@ -778,6 +796,12 @@ static int check_op(const blk_op* A) {
   if (A->kind == BLK_OP_CSR) {
     if (!A->rowptr || !A->colind || !A->val) return fail(BLK_EINVAL, "CSR pointer is NULL");
     if (A->nnz < 0 || A->nnz > (int64_t)0x7fffffff) return fail(BLK_EINVAL, "bad nnz");
+    if (A->structure < BLK_STRUCT_UNKNOWN || A->structure > BLK_STRUCT_GRID)
+      return fail(BLK_EINVAL, "unknown structure %d", (int)A->structure);
+    if (A->structure == BLK_STRUCT_GRID &&
+        (A->grid[0] < 2 || A->grid[1] < 2 || A->grid[2] < 1 || A->grid[0] > A->n ||
+         A->grid[1] > A->n || A->grid[2] > A->n || A->grid[0] * A->grid[1] * A->grid[2] != A->n))
+      return fail(BLK_EINVAL, "grid dimensions do not match n");
   } else if (A->kind == BLK_OP_DENSE) {
     if (!A->dense) return fail(BLK_EINVAL, "dense pointer is NULL");
     if (A->ld < A->n) return fail(BLK_EINVAL, "dense ld < n");
@@ -796,7 +820,64 @@ static DevOp<double> op64(const blk_op* A) {
   o.val = reinterpret_cast<const z64*>(A->val);
   o.dense = reinterpret_cast<const z64*>(A->dense);
   o.ld = A->ld;
+  if (A->kind == BLK_OP_CSR && A->structure == BLK_STRUCT_GRID) {
+    o.gnx = (int)A->grid[0];
+    o.gny = (int)A->grid[1];
+    o.gnz = (int)A->grid[2];
+  }
   return o;
+}
+
+// Grid-stencil detection: the dimensions come from row 0 (its columns are
+// 0, 1, nx and, in 3D, nx ny); every row is then checked on the device.
+// Returns true with (nx, ny, nz) when the whole pattern matches.
+static bool analyze_grid(const blk_op* A, hipStream_t s, int64_t dims[3]) {
+  if (A->kind != BLK_OP_CSR || A->n < 4) return false;
+  int32_t rp[2];
+  HIPCHK(hipMemcpyAsync(rp, A->rowptr, sizeof rp, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const int len = rp[1] - rp[0];
+  if (rp[0] < 0 || (len != 3 && len != 4) || (int64_t)rp[1] > A->nnz) return false;
+  int32_t col[4];
+  HIPCHK(hipMemcpyAsync(col, A->colind + rp[0], sizeof(int32_t) * len, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const int64_t n = A->n;
+  if (col[0] != 0 || col[1] != 1) return false;
+  const int64_t nx = col[2];
+  if (nx < 2 || nx > n) return false;
+  int64_t ny, nz;
+  if (len == 4) {
+    const int64_t nxy = col[3];
+    if (nxy % nx != 0 || n % nxy != 0) return false;
+    ny = nxy / nx;
+    nz = n / nxy;
+    if (nz < 2) return false;
+  } else {
+    if (n % nx != 0) return false;
+    ny = n / nx;
+    nz = 1;
+  }
+  if (ny < 2) return false;
+  int* bad = nullptr;
+  HIPCHK(hipMalloc(&bad, sizeof(int)));
+  int h = 1;
+  try {
+    HIPCHK(hipMemsetAsync(bad, 0, sizeof(int), s));
+    k_grid_check<<<(unsigned)((n + NT - 1) / NT), NT, 0, s>>>(n, A->rowptr, A->colind, (int)nx, (int)ny,
+                                                            (int)nz, bad);
+    LAUNCH_CHECK();
+    HIPCHK(hipMemcpyAsync(&h, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+  } catch (...) {
+    (void)hipFree(bad);
+    throw;
+  }
+  HIPCHK(hipFree(bad));
+  if (h != 0) return false;
+  dims[0] = nx;
+  dims[1] = ny;
+  dims[2] = nz;
+  return true;
 }
 
 static int solve_entry(bool cocr, const blk_op* A, int64_t p, const blk_z* B, int64_t ldb,
@@ -840,6 +921,14 @@ static int solve_entry(bool cocr, const blk_op* A, int64_t p, const blk_z* B, in
     const int hist_len = maxit + 1;
     ctx_alloc(c, pool, n, pi, maxit, s);
     DevOp<double> A64 = op64(A);
+    if (A->kind == BLK_OP_CSR && A->structure == BLK_STRUCT_UNKNOWN) {
+      int64_t d[3];
+      if (analyze_grid(A, s, d)) {
+        A64.gnx = (int)d[0];
+        A64.gny = (int)d[1];
+        A64.gnz = (int)d[2];
+      }
+    }
     const z64* Bz = reinterpret_cast<const z64*>(B);
     const z64* X0z = reinterpret_cast<const z64*>(X0);
     z64* Xz = reinterpret_cast<z64*>(X);
@@ -898,6 +987,33 @@ int32_t blk_cocr_solve(const blk_op* A, int64_t p, const blk_z* B, int64_t ldb, 
                        int64_t ldx, double* res_hist, int32_t* iters, double* true_relres) {
   return solve_entry(true, A, p, B, ldb, X0, ldx0, tol, maxit, opts, X, ldx, res_hist, iters,
                      true_relres);
+}
+
+int32_t blk_op_analyze(blk_op* A, void* stream) {
+  g_err.clear();
+  if (!A) return fail(BLK_EINVAL, "A is NULL");
+  const int32_t saved = A->structure;
+  A->structure = BLK_STRUCT_UNKNOWN;
+  int rc = check_op(A);
+  if (rc) {
+    A->structure = saved;
+    return rc;
+  }
+  try {
+    int64_t d[3] = {0, 0, 0};
+    if (analyze_grid(A, (hipStream_t)stream, d)) {
+      A->structure = BLK_STRUCT_GRID;
+      for (int k = 0; k < 3; ++k) A->grid[k] = d[k];
+    } else {
+      A->structure = BLK_STRUCT_GENERAL;
+      for (int k = 0; k < 3; ++k) A->grid[k] = 0;
+    }
+    return BLK_OK;
+  } catch (const HipError& e) {
+    A->structure = saved;
+    if (e.e == hipErrorOutOfMemory) return fail(BLK_ENOMEM, "%s: %s", e.what, hipGetErrorString(e.e));
+    return fail(BLK_EHIP, "%s: %s", e.what, hipGetErrorString(e.e));
+  }
 }
 
 int32_t blk_spmm_z(const blk_op* A, int64_t p, const blk_z* Z, int64_t ldz, const blk_z* C,

@@ -427,3 +427,100 @@ def test_refine_restarts(pkg, cfg1, method):
     # B - A X in FP64 is itself accurate to about eps |A| |X| / |B|
     trr = O.true_relres(A, B, t2.X.cpu().numpy())
     assert abs(trr - t2.true_relres) <= 1e-6 * trr + 1e-14
+
+
+# ---------------------------------------------------------------------------
+# Grid-stencil operators: pattern analysis and the 2.5D blocked product
+# ---------------------------------------------------------------------------
+
+GRID_SHAPES = [(13, 11, 9), (8, 4, 70), (37, 29, 1), (16, 16, 33)]
+
+
+@pytest.mark.parametrize("dims", GRID_SHAPES)
+def test_grid_analyze_detects(pkg, dev, dims):
+    A = W.grid_stencil_random(*dims, seed=3)
+    Ad = pkg.CsrOperator.from_arrays(A.rowptr, A.colind, A.val, device=dev).analyze()
+    assert Ad.structure == pkg._capi.BLK_STRUCT_GRID
+    assert Ad.grid == dims
+
+
+def test_grid_analyze_rejects(pkg, dev):
+    A = W.grid_stencil_random(9, 7, 5, seed=4)
+    # one row with a missing entry
+    r = 100
+    k0, k1 = A.rowptr[r], A.rowptr[r + 1]
+    colind = np.delete(A.colind, k0 + 1)
+    val = np.delete(A.val, k0 + 1)
+    rowptr = A.rowptr.copy()
+    rowptr[r + 1:] -= 1
+    Ad = pkg.CsrOperator.from_arrays(rowptr, colind, val, device=dev).analyze()
+    assert Ad.structure == pkg._capi.BLK_STRUCT_GENERAL
+    # one row with its columns out of order
+    colind = A.colind.copy()
+    colind[k0], colind[k0 + 1] = colind[k0 + 1], colind[k0]
+    Ad = pkg.CsrOperator.from_arrays(A.rowptr, colind, A.val, device=dev).analyze()
+    assert Ad.structure == pkg._capi.BLK_STRUCT_GENERAL
+    # not a grid at all
+    B = W.random_complex_symmetric(60, seed=1)
+    rows, cols = np.nonzero(np.abs(B) > 0.8)
+    rowptr = np.searchsorted(rows, np.arange(61)).astype(np.int32)
+    Bd = pkg.CsrOperator.from_arrays(rowptr, cols.astype(np.int32), B[rows, cols], device=dev)
+    assert Bd.analyze().structure == pkg._capi.BLK_STRUCT_GENERAL
+
+
+@pytest.mark.parametrize("dims", GRID_SHAPES)
+@pytest.mark.parametrize("p", [17, 32])
+def test_grid_spmm_matches_oracle(pkg, dev, dims, p):
+    """The 2.5D product against the oracle's CSR product, element by element:
+    tiles and z-chunks that do not divide the grid, 2D grids, padded columns."""
+    A = W.grid_stencil_random(*dims, seed=5)
+    Ad = pkg.CsrOperator.from_arrays(A.rowptr, A.colind, A.val, device=dev).analyze()
+    assert Ad.structure == pkg._capi.BLK_STRUCT_GRID
+    Z = W.cgauss(A.n, p, seed=6)
+    Cm = W.cgauss(A.n, p, seed=7)
+    Zd, Cd = torch.as_tensor(Z, device=dev), torch.as_tensor(Cm, device=dev)
+    ref = O.apply(O.as_operator(A), Z)
+    Y = pkg.blk_spmm_z(Ad, Zd).cpu().numpy()
+    assert np.max(np.abs(Y - ref)) <= 1e-13 * np.max(np.abs(ref))
+    Y2, G = pkg.blk_spmm_z(Ad, Zd, gram=True)
+    assert np.array_equal(Y2.cpu().numpy(), Y)
+    assert _relerr(G, O.gram_t(Z, ref)) < 1e-13
+    Y3 = pkg.blk_spmm_z(Ad, Zd, Cd).cpu().numpy()
+    assert np.max(np.abs(Y3 - (Cm - ref))) <= 1e-13 * np.max(np.abs(ref))
+
+
+def test_grid_and_general_paths_agree(pkg, dev):
+    A = W.helmholtz3d(20, 5.0, 0.02)
+    Z = torch.as_tensor(W.cgauss(A.n, 32, seed=8), device=dev)
+    gen = pkg.CsrOperator.from_arrays(A.rowptr, A.colind, A.val, device=dev)
+    gen.structure = pkg._capi.BLK_STRUCT_GENERAL
+    grd = pkg.CsrOperator.from_arrays(A.rowptr, A.colind, A.val, device=dev).analyze()
+    assert grd.grid == (20, 20, 20)
+    a = pkg.blk_spmm_z(gen, Z).cpu().numpy()
+    b = pkg.blk_spmm_z(grd, Z).cpu().numpy()
+    assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(a))
+    # solves: the pattern is analysed inside the call unless told not to
+    B = torch.as_tensor(W.cgauss(A.n, 32, seed=9), device=dev)
+    r1 = pkg.blk_cocr_solve(gen, B, tol=1e-8, maxit=500)
+    r2 = pkg.blk_cocr_solve(pkg.CsrOperator.from_arrays(A.rowptr, A.colind, A.val, device=dev), B,
+                            tol=1e-8, maxit=500)
+    assert r1.status == r2.status == pkg.BLK_CONVERGED
+    # the two products sum in different orders; the recurrences amplify that
+    # (to ~1e-5 relative in the history by iteration 40 on this operator), so
+    # the histories are compared early and the answers by their residuals
+    k = min(20, r1.iters, r2.iters)
+    assert np.max(np.abs(r1.hist[:k] - r2.hist[:k]) / r1.hist[:k]) < 1e-9
+    assert max(r1.true_relres, r2.true_relres) < 1.5e-8
+    assert _relerr(r2.X.cpu().numpy(), r1.X.cpu().numpy()) < 1e-5
+
+
+def test_grid_mixed_precision(pkg, dev):
+    """complex64 inner solves through the 2.5D product (p = 32)."""
+    A = W.config2_operator(12)
+    B = W.cgauss(A.n, 32, seed=10)
+    Ad = pkg.CsrOperator.from_arrays(A.rowptr, A.colind, A.val, device=dev)
+    r = pkg.blk_cocr_solve(Ad, torch.as_tensor(B, device=dev), tol=1e-9, maxit=2000,
+                           precision="mixed")
+    assert r.status == pkg.BLK_CONVERGED, r.status_name
+    assert r.true_relres <= 1e-9
+    assert O.true_relres(A, B, r.X.cpu().numpy()) <= 1.01e-9

@@ -113,6 +113,27 @@ def _stencil_csr(dims: tuple[int, ...], h: float, k: float, delta) -> Csr:
     return Csr(n=n, rowptr=rowptr.astype(np.int32), colind=colind, val=val)
 
 
+def grid_stencil_random(nx: int, ny: int, nz: int, seed: int) -> Csr:
+    """The 7-point pattern (5-point when nz == 1) of a lexicographic
+    nx x ny x nz grid (x fastest, columns ascending in each row) with complex
+    Gaussian entries (seed): an input for pattern and product tests."""
+    n = nx * ny * nz
+    idx = np.arange(n, dtype=np.int64)
+    x, y, z = idx % nx, (idx // nx) % ny, idx // (nx * ny)
+    sxy = nx * ny
+    cand = [(z > 0, -sxy), (y > 0, -nx), (x > 0, -1), (np.ones(n, bool), 0),
+            (x < nx - 1, 1), (y < ny - 1, nx), (z < nz - 1, sxy)]
+    mask = np.stack([m for m, _ in cand], axis=1)
+    cols = np.stack([idx + o for _, o in cand], axis=1)
+    counts = mask.sum(axis=1)
+    rowptr = np.zeros(n + 1, dtype=np.int32)
+    rowptr[1:] = np.cumsum(counts)
+    colind = cols[mask].astype(np.int32)
+    g = np.random.default_rng(seed).standard_normal((len(colind), 2))
+    val = (g[:, 0] + 1j * g[:, 1]) / math.sqrt(2.0)
+    return Csr(n, rowptr, colind, val)
+
+
 def helmholtz2d(N: int, k: float, delta) -> Csr:
     """5-point -Laplacian_h - k^2(1+i delta) I on an N x N interior grid."""
     return _stencil_csr((N, N), 1.0 / (N + 1), k, delta)
