@@ -13,7 +13,7 @@
 // the operand layout a Gram Y^T Y needs when the reduction index is the row:
 // for each v the 4 rows {4v + l/16} form one k-step.  The Grams of the
 // freshly updated block are therefore formed from registers, with no extra
-// memory traffic.  Coefficients sit in LDS as three real planes (Re, Im, -Im).
+// memory traffic.  Coefficients sit in LDS as two real planes (Re, Im).
 #pragma once
 
 #include "common.hpp"
@@ -26,14 +26,7 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 #ifndef MF_WAVES
 #define MF_WAVES 2
 #endif
-#ifndef MF_SCHED
-#define MF_SCHED 0
-#endif
-#if MF_SCHED
-#define MF_STEP_BARRIER() __builtin_amdgcn_sched_barrier(0)
-#else
-#define MF_STEP_BARRIER() ((void)0)
-#endif
+
 
 __device__ inline d4 mfma64(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -45,7 +38,6 @@ struct MfCoef {
   static constexpr int LD = PP + 1;  // padded row
   double re[PP * LD];
   double im[PP * LD];
-  double nim[PP * LD];
 };
 
 // Load the p x p FP64 coefficient (row-major, ld p) into LDS planes, scaled
@@ -58,7 +50,6 @@ __device__ inline void mf_load_coef(MfCoef<JB>* C, const z64* src, int p, double
     z64 v = (k < p && j < p) ? src[k * p + j] : czero<double>();
     C->re[k * LD + j] = sign * v.re;
     C->im[k * LD + j] = sign * v.im;
-    C->nim[k * LD + j] = -sign * v.im;
   }
 }
 
@@ -138,8 +129,11 @@ __device__ inline void mf_store_D(z64* X, int ld, int64_t r0, int64_t n, int p, 
   }
 }
 
-// acc += Z C with Z in the A layout and C in LDS.  KMAX limits the k-steps
-// (a triangular C needs only the first ones for the low column block).
+// acc += Z C with Z in the A layout and C in LDS:
+//   Re += Zr Cr + Zi (-Ci),  Im += Zr Ci + Zi Cr.
+// (Three-product complex forms ran no faster here: these passes are bound by
+// memory and latency more than by the matrix cores.)
+// UPPER: C is upper triangular, so the k-steps below a column block vanish.
 template <int JB, bool UPPER>
 __device__ inline void mf_mma(d4 (&cr)[JB], d4 (&ci)[JB], const double (&ar)[4 * JB],
                               const double (&ai)[4 * JB], const MfCoef<JB>* C) {
@@ -150,17 +144,13 @@ __device__ inline void mf_mma(d4 (&cr)[JB], d4 (&ci)[JB], const double (&ar)[4 *
   for (int jb = 0; jb < JB; ++jb) {
 #pragma unroll
     for (int s = 0; s < 4 * JB; ++s) {
-      // for an upper-triangular C, rows k > 16 jb + 15 of column block jb vanish
       if (UPPER && 4 * s > 16 * jb + 15) continue;
       const int k = 4 * s + kr, j = 16 * jb + jc;
-      const double br = C->re[k * LD + j], bi = C->im[k * LD + j], bn = C->nim[k * LD + j];
+      const double br = C->re[k * LD + j], bi = C->im[k * LD + j];
       cr[jb] = mfma64(ar[s], br, cr[jb]);
-      cr[jb] = mfma64(ai[s], bn, cr[jb]);
+      cr[jb] = mfma64(ai[s], -bi, cr[jb]);
       ci[jb] = mfma64(ar[s], bi, ci[jb]);
       ci[jb] = mfma64(ai[s], br, ci[jb]);
-      // keep the coefficient reads next to their products: batching them
-      // ahead would hold ~100 registers and cut occupancy
-      MF_STEP_BARRIER();
     }
   }
 }
@@ -265,7 +255,7 @@ __device__ inline void mf_tiles(int64_t n, int64_t& t0, int64_t& t1) {
 // LDS of a kernel: coefficient planes, later reused as the Gram scratch.
 template <int JB>
 constexpr int mf_coef_doubles() {
-  return 3 * (16 * JB) * (16 * JB + 1);
+  return 2 * (16 * JB) * (16 * JB + 1);
 }
 template <int JB>
 constexpr int mf_scratch_doubles() {
