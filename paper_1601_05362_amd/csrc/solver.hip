@@ -200,8 +200,12 @@ static void apply_op(Ctx& c, const DevOp<T>& A, const cx<T>* Z, int ldz, const c
         const int64_t units = grid_units(A.gnx, A.gny, A.gnz);
         const int64_t G = (GRAM || NORM) ? std::min<int64_t>(units, std::max(c.G, c.Gs)) : units;
         if (GRAM || NORM) c.nblk[role] = (int)G;
-        k_spmm_grid<T, SUB, STORE, GRAM, NORM><<<(unsigned)G, GT, 0, c.s>>>(
-            A.gnx, A.gny, A.gnz, A.rowptr, A.val, Z, ldz, C, ldc, Y, ldy, c.p, part, E, st, gate);
+        if constexpr (GRAM)
+          k_spmm_grid_walk<T, SUB, STORE, GRAM, NORM><<<(unsigned)G, GT, 0, c.s>>>(
+              A.gnx, A.gny, A.gnz, A.rowptr, A.val, Z, ldz, C, ldc, Y, ldy, c.p, part, E, st, gate);
+        else
+          k_spmm_grid<T, SUB, STORE, GRAM, NORM><<<(unsigned)G, GT, 0, c.s>>>(
+              A.gnx, A.gny, A.gnz, A.rowptr, A.val, Z, ldz, C, ldc, Y, ldy, c.p, part, E, st, gate);
         LAUNCH_CHECK();
         return;
       }
