@@ -757,8 +757,10 @@ static SolveOut run_mixed(Ctx& c, Pool& pool, const blk_op* A, const DevOp<doubl
     const double itol = std::max(o.inner_tol, 0.5 * tol / rel);
     // complex64 storage, FP64 accumulation of every Gram: the unconjugated
     // forms cancel heavily and FP32 sums lose the recurrences' coefficients.
+    // An inner run whose monitored residual grows tenfold has diverged (the
+    // FP64 iteration's early plateau stays below twice its start).
     SolveOut in = run_solve<float, double>(c, A32, cocr, o.rq != 0, Rf, pi, nullptr, 0, D, pi, itol,
-                                           cap, o.check_every, bk, 1e3);
+                                           cap, o.check_every, bk, 10.0);
     for (int k = 1; k <= in.iters && (int)so.hist.size() < hist_len; ++k)
       so.hist.push_back(rel * in.hist[k]);
     total += in.iters;

@@ -82,3 +82,28 @@ def test_argument_validation_rejects_before_device_work():
     assert lib.blk_gram_z(10, 0, fake, 1, fake, 1, 0, fake, None) == _capi.BLK_EINVAL
     assert lib.blk_spmm_c(0, 0, fake, fake, fake, 1, fake, 1, fake + 4096, 1, None) == _capi.BLK_EINVAL
     assert lib.blk_thin_qr_z(10, 2, fake, 1, fake, 2, fake, None) == _capi.BLK_EINVAL
+
+
+def test_structure_validation_rejects_before_device_work():
+    """A grid structure whose dimensions do not multiply to n, or an unknown
+    structure code, is BLK_EINVAL; blk_op_analyze leaves the operator as it
+    was on EINVAL."""
+    from paper_1601_05362_amd import _capi
+
+    lib = _capi.load()
+    fake = 0x1000
+    it = C.c_int32(0)
+    grid = (C.c_int64 * 3)(4, 4, 3)  # 48 != 50
+    op = _capi.BlkOp(_capi.BLK_OP_CSR, _capi.BLK_STRUCT_GRID, 50, 200, fake, fake, fake, None, 0, grid)
+    assert lib.blk_cocr_solve(C.byref(op), 2, fake, 2, None, 0, 1e-8, 10, None, fake + 8192, 2, None,
+                              C.byref(it), None) == _capi.BLK_EINVAL
+    assert "grid" in lib.blk_last_error().decode()
+    assert lib.blk_spmm_z(C.byref(op), 2, fake, 2, None, 0, fake + 8192, 2, None, None) == _capi.BLK_EINVAL
+    op.structure = 7
+    assert lib.blk_spmm_z(C.byref(op), 2, fake, 2, None, 0, fake + 8192, 2, None, None) == _capi.BLK_EINVAL
+    # analysis of an invalid operator: EINVAL, structure untouched
+    bad = _capi.BlkOp(_capi.BLK_OP_CSR, _capi.BLK_STRUCT_GENERAL, 0, 0, None, None, None, None, 0,
+                      (C.c_int64 * 3)(0, 0, 0))
+    assert lib.blk_op_analyze(C.byref(bad), None) == _capi.BLK_EINVAL
+    assert bad.structure == _capi.BLK_STRUCT_GENERAL
+    assert lib.blk_op_analyze(None, None) == _capi.BLK_EINVAL
