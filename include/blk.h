@@ -168,7 +168,10 @@ int32_t blk_cocr_solve(const blk_op *A, int64_t p, const blk_z *B, int64_t ldb, 
  * Y = A Z, or Y = C - A Z when C is not NULL.  If gram is not NULL it receives
  * [host] the unconjugated p x p form Z^T Y, row-major complex128.
  * Y must not overlap Z.  Returns BLK_OK or an error.  Without gram the call
- * allocates nothing and does not wait: the product is queued on `stream`.
+ * allocates nothing and does not wait: the product is queued on `stream` --
+ * except for a DENSE operator with p > 16, whose matrix-core product needs a
+ * split-K workspace (4 n 32 complex128): that call allocates it and returns
+ * when the product is done.
  */
 int32_t blk_spmm_z(const blk_op *A, int64_t p, const blk_z *Z, int64_t ldz, const blk_z *C,
                    int64_t ldc, blk_z *Y, int64_t ldy, blk_z *gram, void *stream);

@@ -33,6 +33,7 @@
 #include "rowpass.hpp"
 #include "rowpass_mfma.hpp"
 #include "grid.hpp"
+#include "dense_mf.hpp"
 #include "spmm.hpp"
 
 namespace blk {
@@ -129,6 +130,7 @@ struct Ctx {
   DevState* st = nullptr;
   double* hist = nullptr;  // device, maxit + 2 entries
   int hist_cap = 0;
+  z64* dws = nullptr;      // split-K partials of the dense product (DSPLIT x n x 32)
 };
 
 // Launch geometry of a row pass over n rows of p columns.
@@ -224,6 +226,30 @@ static void apply_op(Ctx& c, const DevOp<T>& A, const cx<T>* Z, int ldz, const c
           c.n, A.rowptr, A.colind, A.val, Z, ldz, C, ldc, Y, ldy, c.p, part, E, st, gate, remap);
     } else {
       if (GRAM || NORM) c.nblk[role] = c.G;
+      if constexpr (std::is_same<T, double>::value && PP == 32) {
+        if (c.dws) {
+          // matrix-core product into split-K partials, then their fixed-order
+          // sum with the epilogues; the Gram Z^T Y reads the stored Y
+          // (the casts only name T = double; this branch exists for it alone)
+          const z64* Ad = reinterpret_cast<const z64*>(A.dense);
+          const z64* Zd = reinterpret_cast<const z64*>(Z);
+          const z64* Cd = reinterpret_cast<const z64*>(C);
+          z64* Yd = reinterpret_cast<z64*>(Y);
+          k_dense_mf<<<(unsigned)dense_blocks(c.n), NT, 0, c.s>>>(c.n, Ad, A.ld, Zd, ldz, c.p, c.dws,
+                                                                  st, gate);
+          LAUNCH_CHECK();
+          k_dense_fin<SUB, STORE, NORM><<<c.G, NT, 0, c.s>>>(c.n, c.p, c.dws, Cd, ldc, Yd, ldy, part,
+                                                             E, st, gate);
+          LAUNCH_CHECK();
+          if (GRAM) {
+            static_assert(!GRAM || STORE, "the Gram of a dense product reads the stored Y");
+            k_gram_mf<2, G_UNCONJ, false><<<c.G, NT, 0, c.s>>>(c.n, c.p, Zd, ldz, Yd, ldy, part, E, st,
+                                                               gate);
+          }
+          LAUNCH_CHECK();
+          return;
+        }
+      }
       k_dense<T, PP, SUB, STORE, GRAM, NORM><<<c.G, NT, 0, c.s>>>(
           c.n, A.dense, A.ld, Z, ldz, C, ldc, Y, ldy, c.p, part, E, st, gate);
     }
@@ -926,6 +952,8 @@ static int solve_entry(bool cocr, const blk_op* A, int64_t p, const blk_z* B, in
     Ctx c;
     const int hist_len = maxit + 1;
     ctx_alloc(c, pool, n, pi, maxit, s);
+    if (A->kind == BLK_OP_DENSE && pi > 16)
+      c.dws = pool.get<z64>(sizeof(z64) * (size_t)DSPLIT * n * 32);
     DevOp<double> A64 = op64(A);
     if (A->kind == BLK_OP_CSR && A->structure == BLK_STRUCT_UNKNOWN) {
       int64_t d[3];
@@ -1048,9 +1076,11 @@ int32_t blk_spmm_z(const blk_op* A, int64_t p, const blk_z* Z, int64_t ldz, cons
       k_state_init<<<1, 64, 0, s>>>(c.st, (int)p, 0, 1.0, INFINITY);
       LAUNCH_CHECK();
     } else {
-      // no workspace at all: the product alone, asynchronous on `stream`
+      // no workspace (CSR): the product alone, asynchronous on `stream`
       ctx_geometry(c, n, (int)p, s);
     }
+    // a dense operator at p > 16 needs the split-K partials
+    if (A->kind == BLK_OP_DENSE && p > 16) c.dws = pool.get<z64>(sizeof(z64) * (size_t)DSPLIT * n * 32);
     if (gram) {
       if (C)
         apply_op<double, true, true, true, false>(c, A64, Zz, (int)ldz, Cz, (int)ldc, Yz, (int)ldy,
@@ -1079,7 +1109,7 @@ int32_t blk_spmm_z(const blk_op* A, int64_t p, const blk_z* Z, int64_t ldz, cons
         apply_op<double, false, true, false, false>(c, A64, Zz, (int)ldz, nullptr, 0, Yz, (int)ldy,
                                                     RO_S, 0, -1);
     }
-    if (gram) HIPCHK(hipStreamSynchronize(s));
+    if (gram || c.dws) HIPCHK(hipStreamSynchronize(s));  // before the workspace is freed
     return BLK_OK;
   } catch (const HipError& e) {
     if (e.e == hipErrorOutOfMemory) return fail(BLK_ENOMEM, "%s: %s", e.what, hipGetErrorString(e.e));

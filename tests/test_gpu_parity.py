@@ -524,3 +524,39 @@ def test_grid_mixed_precision(pkg, dev):
     assert r.status == pkg.BLK_CONVERGED, r.status_name
     assert r.true_relres <= 1e-9
     assert O.true_relres(A, B, r.X.cpu().numpy()) <= 1.01e-9
+
+
+# ---------------------------------------------------------------------------
+# Dense operators at p > 16: the matrix-core product with split-K partials
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,p", [(1000, 32), (1024, 20), (77, 17)])
+def test_dense_mfma_apply_matches_oracle(pkg, dev, n, p):
+    """Element-wise against the oracle's product: ragged row blocks and K
+    ranges (n not a multiple of 64 or 32), padded columns, C - A Z, the Gram."""
+    k = 2 * math.pi * 1.5
+    A = W.greens_sphere(n, k)
+    Z = W.cgauss(n, p, seed=11)
+    Cm = W.cgauss(n, p, seed=12)
+    Ad = pkg.DenseOperator(torch.as_tensor(A, device=dev))
+    Zd, Cd = torch.as_tensor(Z, device=dev), torch.as_tensor(Cm, device=dev)
+    ref = O.apply(A, Z)
+    Y = pkg.blk_spmm_z(Ad, Zd).cpu().numpy()
+    assert np.max(np.abs(Y - ref)) <= 1e-13 * np.max(np.abs(ref))
+    Y2, G = pkg.blk_spmm_z(Ad, Zd, gram=True)
+    assert np.max(np.abs(Y2.cpu().numpy() - ref)) <= 1e-13 * np.max(np.abs(ref))
+    assert _relerr(G, O.gram_t(Z, ref)) < 1e-12
+    Y3 = pkg.blk_spmm_z(Ad, Zd, Cd).cpu().numpy()
+    assert np.max(np.abs(Y3 - (Cm - ref))) <= 1e-13 * np.max(np.abs(ref))
+
+
+def test_dense_mfma_solver_parity(pkg, dev):
+    """Block COCR_rq on a dense Green's operator at p = 32 against the oracle."""
+    n, p = 1024, 32
+    k = 2 * math.pi * 1.5
+    A = W.greens_sphere(n, k)
+    B = W.plane_waves3d(W.fibonacci_sphere(n), k, p) + 1e-3 * W.cgauss(n, p, seed=13)
+    Ad = pkg.DenseOperator(torch.as_tensor(A, device=dev))
+    ref, H, it_tol, x_tol = _oracle_with_spread("cocr_rq", A, B, tol=1e-8, maxit=500, runs=4)
+    r = pkg.blk_cocr_solve(Ad, torch.as_tensor(B, device=dev), tol=1e-8, maxit=500)
+    _check_parity(r, ref, H, it_tol, x_tol)
