@@ -140,6 +140,8 @@ def main():
     ap.add_argument("--cpu-sample-iters", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-mixed", action="store_true")
+    ap.add_argument("--dense", type=int, default=0, metavar="N",
+                    help="also time the dense Green's-function product at n = N (p as above)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -184,6 +186,34 @@ def main():
         Yc.copy_(Zd)
     torch.cuda.synchronize()
     del Zd, Zc, Yc
+
+    # --- optional: the dense Green's-function operator (second experiment) -----
+    dense = None
+    if args.dense:
+        nd = args.dense
+        t0 = time.perf_counter()
+        Ah = W.greens_sphere(nd, 2.0 * math.pi * 8.0)
+        Dd = pkg.DenseOperator(torch.as_tensor(Ah, device=dev))
+        del Ah
+        Zd = torch.as_tensor(W.cgauss(nd, p, seed=5), device=dev)
+        Yd = torch.empty_like(Zd)
+        log(f"[bench] dense operator n={nd} built in {time.perf_counter() - t0:.1f}s")
+        stream = torch.cuda.current_stream()
+        pkg.blk_spmm_z(Dd, Zd, out=Yd)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(5):
+            pkg.blk_spmm_z(Dd, Zd, out=Yd)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 5
+        tf = 8.0 * nd * nd * p / (ms * 1e-3) / 1e12
+        dense = {"n": nd, "p": p, "ms": round(ms, 4), "TFLOPs": round(tf, 2),
+                 "frac_fp64_peak": round(tf / 78.6, 4),
+                 "A_GBs": round(16.0 * nd * nd / (ms * 1e-3) / 1e9, 1)}
+        log(f"[bench] dense c128 product n={nd} p={p}: {ms:.3f} ms, {tf:.1f} TFLOP/s")
+        del Dd, Zd, Yd
+        torch.cuda.synchronize()
 
     # --- solves -----------------------------------------------------------------
     def step():
@@ -267,6 +297,7 @@ def main():
             "avg_launch_ms": round(t_spmm * 1e3, 4),
         },
         "cpu_baseline": None,
+        "dense_product": dense,
     }
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
