@@ -180,6 +180,13 @@ def main():
     gbs64, gbs32 = b64 / t_spmm / 1e9, b32 / t_spmm32 / 1e9
     log(f"[bench] spmm c128 p={p}: {t_spmm * 1e3:.3f} ms, {gbs64:.0f} GB/s ({gbs64 / HBM_PEAK_GBS:.1%} of peak); "
         f"c64: {t_spmm32 * 1e3:.3f} ms, {gbs32:.0f} GB/s ({gbs32 / HBM_PEAK_GBS:.1%})")
+    # the same operator with p = 8 columns (the grid kernel serves p > 16)
+    Z8 = torch.as_tensor(W.cgauss(A.n, 8, seed=6), device=dev)
+    t_spmm8 = time_spmm(pkg, torch, Ad, Z8, args.spmm_reps, c64=False)
+    b8 = spmm_bytes(A.n, A.nnz, 8, 16)
+    gbs8 = b8 / t_spmm8 / 1e9
+    log(f"[bench] spmm c128 p=8: {t_spmm8 * 1e3:.3f} ms, {gbs8:.0f} GB/s ({gbs8 / HBM_PEAK_GBS:.1%})")
+    del Z8
     # a plain copy of known size: the calibration point for HBM byte counters
     Yc = torch.empty_like(Zd)
     for _ in range(3):
@@ -284,6 +291,8 @@ def main():
         "spmm_c128_GBs": round(gbs64, 1),
         "spmm_c64_ms": round(t_spmm32 * 1e3, 4),
         "spmm_c64_GBs": round(gbs32, 1),
+        "spmm_c128_p8_ms": round(t_spmm8 * 1e3, 4),
+        "spmm_c128_p8_GBs": round(gbs8, 1),
         "roofline": {
             "bound": "hbm",
             "kernel": (f"k_spmm_grid complex128 p={p} (2.5D, grid-stencil pattern)" if grid_path
