@@ -29,6 +29,29 @@ __host__ __device__ inline int64_t grid_units(int nx, int ny, int nz) {
   return (int64_t)((nx + GTX - 1) / GTX) * ((ny + GTY - 1) / GTY) * ((nz + GLZ - 1) / GLZ);
 }
 
+// x-y tile of the pipelined product for PP lanes per grid point: GT / PP
+// points, as square as the width 2..32 points per x-run allows.
+template <int PP>
+struct GridTile;
+template <>
+struct GridTile<32> {
+  static constexpr int X = 8, Y = 4;
+};
+template <>
+struct GridTile<16> {
+  static constexpr int X = 8, Y = 8;
+};
+template <>
+struct GridTile<8> {
+  static constexpr int X = 16, Y = 8;
+};
+
+template <int PP>
+__host__ __device__ inline int64_t grid_units_pp(int nx, int ny, int nz) {
+  constexpr int TX = GridTile<PP>::X, TY = GridTile<PP>::Y;
+  return (int64_t)((nx + TX - 1) / TX) * ((ny + TY - 1) / TY) * ((nz + GLZ - 1) / GLZ);
+}
+
 // Verify the stencil pattern: any mismatching row stores 1 to *bad.
 __global__ __launch_bounds__(NT) void k_grid_check(int64_t n, const int32_t* __restrict__ rowptr,
                                                    const int32_t* __restrict__ colind, int nx, int ny,
@@ -75,32 +98,30 @@ __device__ inline void grid_gram16(const z64* zs, const z64* ys, int ib, int jb,
 // coefficients are in flight, and loads are issued in the order they are
 // consumed (the vector-memory counter retires them in order).  The
 // coefficients of a plane arrive as whole x-runs: the rows of one tile line
-// are consecutive, so their stored entries are contiguous in the CSR and 64
-// threads per line fetch them once into LDS.
-template <typename T, bool SUB, bool STORE, bool GRAM, bool NORM>
+// are consecutive, so their stored entries are contiguous in the CSR and one
+// group of loader threads per line fetches them once into LDS.  PP lanes own
+// a grid point's columns (PP = 8, 16, 32 with 128, 64, 32 points per tile);
+// the fused Gram is left to k_spmm_grid_walk.
+template <typename T, int PP, bool SUB, bool STORE, bool NORM>
 __global__ __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(8))) void k_spmm_grid(
     int nx, int ny, int nz, const int32_t* __restrict__ rowptr, const cx<T>* __restrict__ val,
     const cx<T>* __restrict__ Z, int ldz, const cx<T>* __restrict__ Cm, int ldc,
     cx<T>* __restrict__ Y, int ldy, int p, double* part, int E, const DevState* st, int gate) {
   if (st && gate >= st->stop_iter) return;
+  constexpr int GTX = GridTile<PP>::X, GTY = GridTile<PP>::Y;
+  static_assert(GTX * GTY * PP == GT, "one thread row per tile point");
   constexpr int W = GTX + 2, H = GTY + 2, NH = 2 * (GTX + GTY);
-  constexpr int PL = W * H * 32;  // plane + halo, in cx<T>
-  constexpr int RS = 64;          // coefficient slots per x-run (GTX rows x at most 7)
-  static_assert(GTX * 7 <= RS, "x-run coefficients fit their slots");
-  // with GRAM the plane buffer also stages the 32 Z and Y rows (as z64)
-  constexpr int PB = (int)sizeof(cx<T>) * PL, GB = GRAM ? 2 * 32 * 32 * 16 : 0;
-  __shared__ __align__(16) char lds_buf[PB > GB ? PB : GB];
+  static_assert(NH <= GTX * GTY, "one halo point per thread row");
+  constexpr int PL = W * H * PP;                   // plane + halo, in cx<T>
+  constexpr int RS = (GTX * 7 + 31) / 32 * 32;     // coefficient slots per x-run
+  static_assert(GTY * RS <= GT, "one coefficient per loader thread");
+  __shared__ __align__(16) cx<T> pl[PL];
   __shared__ __align__(16) cx<T> coef[GTY * RS];
-  // Gram accumulators of waves 0-3 (block (w >> 1, w & 1)) between planes,
-  // kept in LDS so that no registers stay live across the walk
-  __shared__ __align__(16) double gacc[GRAM ? 4 * 2 * 4 * 64 : 1];
   __shared__ double sh[GT / 64];
-  cx<T>* pl = reinterpret_cast<cx<T>*>(lds_buf);
-  z64* gs = reinterpret_cast<z64*>(lds_buf);
-  const int t = threadIdx.x, c = t & 31, q = t >> 5, w = t >> 6, l = t & 63;
+  const int t = threadIdx.x, c = t % PP, q = t / PP, w = t >> 6;
   const bool cok = c < p;
   const int tilesx = (nx + GTX - 1) / GTX, tilesy = (ny + GTY - 1) / GTY;
-  const int64_t units = grid_units(nx, ny, nz);
+  const int64_t units = grid_units_pp<PP>(nx, ny, nz);
   const int sxy = nx * ny;  // rows fit int32 (n < 2^31 is checked by the caller)
   // halo point owned by thread row q (q < NH): ring of the (W x H) frame
   int hx = 0, hy = 0;
@@ -119,8 +140,6 @@ __global__ __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(8))) void k_
   const int qrun = q / GTX;                     // its x-run (tile line)
   const bool loader = t < GTY * RS;             // coefficient loader: run lj, slot le
   const int lj = t / RS, le = t % RS;
-  if (GRAM && w < 4)
-    for (int k = 0; k < 8; ++k) gacc[(w * 8 + k) * 64 + l] = 0.0;
   double nrm = 0.0;
   for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
     const int bx = (int)(u % tilesx), by = (int)((u / tilesx) % tilesy);
@@ -170,8 +189,8 @@ __global__ __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(8))) void k_
       const cx<T> nn = (in && cok && z + 2 < nz) ? Z[(int64_t)(r0 + sxy * (z + 2)) * ldz + c] : czero<T>();
       const cx<T> hn = (hok && z + 1 < z1) ? Z[(int64_t)(hr0 + sxy * (z + 1)) * ldz + c] : czero<T>();
       // plane z into LDS
-      if (q < NH) pl[(hy * W + hx) * 32 + c] = hcur;
-      pl[(ly * W + lx) * 32 + c] = cur;
+      if (q < NH) pl[(hy * W + hx) * PP + c] = hcur;
+      pl[(ly * W + lx) * PP + c] = cur;
       if (loader) coef[t] = cv;
       __syncthreads();
       cx<T> yv = czero<T>();
@@ -182,11 +201,11 @@ __global__ __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(8))) void k_
         const cx<T>* v = coef + qrun * RS + off0;
         cx<T> acc = czero<T>();
         if (h0) cfma(acc, v[0], prev);
-        if (h1) cfma(acc, v[s1], pl[((ly - 1) * W + lx) * 32 + c]);
-        if (h2) cfma(acc, v[s2], pl[(ly * W + lx - 1) * 32 + c]);
+        if (h1) cfma(acc, v[s1], pl[((ly - 1) * W + lx) * PP + c]);
+        if (h2) cfma(acc, v[s2], pl[(ly * W + lx - 1) * PP + c]);
         cfma(acc, v[s3], cur);
-        if (h4) cfma(acc, v[s4], pl[(ly * W + lx + 1) * 32 + c]);
-        if (h5) cfma(acc, v[s5], pl[((ly + 1) * W + lx) * 32 + c]);
+        if (h4) cfma(acc, v[s4], pl[(ly * W + lx + 1) * PP + c]);
+        if (h5) cfma(acc, v[s5], pl[((ly + 1) * W + lx) * PP + c]);
         if (h6) cfma(acc, v[s6], nxt);
         if (cok) {
           yv = SUB ? csub(Cm[(int64_t)(r0 + sxy * z) * ldc + c], acc) : acc;
@@ -194,28 +213,6 @@ __global__ __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(8))) void k_
         }
       }
       if (NORM) nrm += (double)cabs2(yv);
-      if (GRAM) {
-        __syncthreads();  // the plane has been read; stage the rows over it
-        gs[q * 32 + c] = z64{(double)cur.re, (double)cur.im};
-        gs[32 * 32 + q * 32 + c] = z64{(double)yv.re, (double)yv.im};
-        __syncthreads();
-        if (w < 4) {
-          d4 gr, gi;
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            gr[v] = gacc[(w * 8 + v) * 64 + l];
-            gi[v] = gacc[(w * 8 + 4 + v) * 64 + l];
-          }
-          // rows 0-15, then rows 16-31
-          grid_gram16(gs, gs + 32 * 32, (w >> 1) & 1, w & 1, gr, gi);
-          grid_gram16(gs + 16 * 32, gs + 32 * 32 + 16 * 32, (w >> 1) & 1, w & 1, gr, gi);
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            gacc[(w * 8 + v) * 64 + l] = gr[v];
-            gacc[(w * 8 + 4 + v) * 64 + l] = gi[v];
-          }
-        }
-      }
       __syncthreads();  // LDS is free for the next plane
       prev = cur;
       cur = nxt;
@@ -228,33 +225,15 @@ __global__ __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(8))) void k_
       lc1 = lc2;
     }
   }
-  if (GRAM || NORM) {
-    double* dst = part + (size_t)blockIdx.x * E;
-    if (GRAM) {
-      __syncthreads();
-      if (w < 4) {
-        const int ib = (w >> 1) & 1, jb = w & 1;
-        const int j = 16 * jb + (l & 15);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int i = 16 * ib + 4 * v + (l >> 4);
-          if (i < p && j < p) {
-            dst[2 * (i * p + j)] = gacc[(w * 8 + v) * 64 + l];
-            dst[2 * (i * p + j) + 1] = gacc[(w * 8 + 4 + v) * 64 + l];
-          }
-        }
-      }
-    }
-    if (NORM) {
-      for (int o = 32; o > 0; o >>= 1) nrm += __shfl_xor(nrm, o);
-      __syncthreads();
-      if ((threadIdx.x & 63) == 0) sh[w] = nrm;
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int k = 0; k < GT / 64; ++k) s += sh[k];
-        dst[E - 1] = s;
-      }
+  if (NORM) {
+    for (int o = 32; o > 0; o >>= 1) nrm += __shfl_xor(nrm, o);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[w] = nrm;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (int k = 0; k < GT / 64; ++k) s += sh[k];
+      part[(size_t)blockIdx.x * E + E - 1] = s;
     }
   }
 }

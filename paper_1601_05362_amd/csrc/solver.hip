@@ -195,19 +195,24 @@ static void apply_op(Ctx& c, const DevOp<T>& A, const cx<T>* Z, int ldz, const c
     constexpr int PP = decltype(ppc)::value;
     double* part = (GRAM || NORM) ? c.part[role] : nullptr;
     const DevState* st = c.st;
-    if constexpr (PP == 32) {
-      if (A.kind == BLK_OP_CSR && A.gnx > 0) {
+    if constexpr (PP == 32 || PP == 16 || PP == 8) {
+      if (A.kind == BLK_OP_CSR && A.gnx > 0 && (PP == 32 || !GRAM)) {
         // grid-stencil pattern: 2.5D blocked product; with a reduction the
         // grid is bounded by the partial buffers (blocks loop over units)
-        const int64_t units = grid_units(A.gnx, A.gny, A.gnz);
-        const int64_t G = (GRAM || NORM) ? std::min<int64_t>(units, std::max(c.G, c.Gs)) : units;
-        if (GRAM || NORM) c.nblk[role] = (int)G;
-        if constexpr (GRAM)
+        const int cap = std::max(c.G, c.Gs);
+        if constexpr (GRAM) {
+          const int64_t units = grid_units(A.gnx, A.gny, A.gnz);
+          const int64_t G = std::min<int64_t>(units, cap);
+          c.nblk[role] = (int)G;
           k_spmm_grid_walk<T, SUB, STORE, GRAM, NORM><<<(unsigned)G, GT, 0, c.s>>>(
               A.gnx, A.gny, A.gnz, A.rowptr, A.val, Z, ldz, C, ldc, Y, ldy, c.p, part, E, st, gate);
-        else
-          k_spmm_grid<T, SUB, STORE, GRAM, NORM><<<(unsigned)G, GT, 0, c.s>>>(
+        } else {
+          const int64_t units = grid_units_pp<PP>(A.gnx, A.gny, A.gnz);
+          const int64_t G = NORM ? std::min<int64_t>(units, cap) : units;
+          if (NORM) c.nblk[role] = (int)G;
+          k_spmm_grid<T, PP, SUB, STORE, NORM><<<(unsigned)G, GT, 0, c.s>>>(
               A.gnx, A.gny, A.gnz, A.rowptr, A.val, Z, ldz, C, ldc, Y, ldy, c.p, part, E, st, gate);
+        }
         LAUNCH_CHECK();
         return;
       }

@@ -469,7 +469,7 @@ def test_grid_analyze_rejects(pkg, dev):
 
 
 @pytest.mark.parametrize("dims", GRID_SHAPES)
-@pytest.mark.parametrize("p", [17, 32])
+@pytest.mark.parametrize("p", [5, 8, 13, 16, 17, 32])
 def test_grid_spmm_matches_oracle(pkg, dev, dims, p):
     """The 2.5D product against the oracle's CSR product, element by element:
     tiles and z-chunks that do not divide the grid, 2D grids, padded columns."""
