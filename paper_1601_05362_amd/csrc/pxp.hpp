@@ -38,55 +38,85 @@ __device__ inline z64 cdiv(z64 a, z64 b) {
   }
 }
 
-// The p x p kernels run one workgroup of PXT = PMAX^2 threads; thread t owns
-// entry (i, j) = (t / PMAX, t % PMAX) of a p x p matrix (row-major, ld p),
-// so every elimination step updates all of its entries at once.
-constexpr int PXT = PMAX * PMAX;
-constexpr int PXW = PXT / 64;  // waves
+// The p x p kernels run one workgroup of m^2 threads, m = 8, 16 or 32 the
+// smallest that holds p (px_threads); thread t owns entry (i, j) =
+// (t / m, t % m) of a p x p matrix (row-major, ld p), so every elimination
+// step updates all of its entries at once.  Small blocks get one wave and
+// barriers that cost next to nothing.
+constexpr int PXT = PMAX * PMAX;  // largest workgroup
+constexpr int PXW = PXT / 64;     // its waves
 
-__device__ inline int px_i() { return threadIdx.x / PMAX; }
-__device__ inline int px_j() { return threadIdx.x % PMAX; }
+__host__ __device__ inline int px_threads(int p) { return p <= 4 ? 64 : (p <= 16 ? 256 : PXT); }
+__device__ inline int px_m() { return blockDim.x == 64 ? 8 : (blockDim.x == 256 ? 16 : PMAX); }
+__device__ inline int px_i() { return threadIdx.x / px_m(); }
+__device__ inline int px_j() { return threadIdx.x % px_m(); }
+__device__ inline int px_waves() { return blockDim.x / 64; }
 
-// dst[p x p] = sum of the rows of a reduced Gram, each entry summed over the
-// rows in ascending order (loads issued eight rows at a time).
-__device__ inline void red_load(const Red r, z64* dst, int p) {
-  const int e = threadIdx.x;
-  if (e >= p * p) return;
-  const double* src = r.base + r.off + 2 * e;
+// Sum of rows [s0, s1) of column c of a reduced Gram (ascending, loads
+// issued up to 16 rows at a time).
+__device__ inline z64 red_rows(const Red r, int c, int s0, int s1) {
+  const double* src = r.base + r.off + 2 * c;
   double re = 0.0, im = 0.0;
-  int s = 0;
-  for (; s + 8 <= r.nrows; s += 8) {
-    double vr[8], vi[8];
+  int s = s0;
+  for (; s + 16 <= s1; s += 16) {
+    double vr[16], vi[16];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < 16; ++u) {
       vr[u] = src[(size_t)(s + u) * r.ld];
       vi[u] = src[(size_t)(s + u) * r.ld + 1];
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < 16; ++u) {
       re += vr[u];
       im += vi[u];
     }
   }
-  for (; s < r.nrows; ++s) {
+  for (; s < s1; ++s) {
     re += src[(size_t)s * r.ld];
     im += src[(size_t)s * r.ld + 1];
   }
-  dst[e] = z64{re, im};
+  return z64{re, im};
 }
 
-// Sum of one column of a reduced scalar (rows in ascending order).
-__device__ inline double red_scalar(const Red r) {
-  double s = 0.0;
-  int k = 0;
-  for (; k + 8 <= r.nrows; k += 8) {
-    double v[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = r.base[(size_t)(k + u) * r.ld + r.off];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) s += v[u];
+// dst[p x p] = sum of the rows of a reduced Gram.  The workgroup's threads
+// split each entry's rows into nseg contiguous segments (nseg = threads per
+// entry); each segment is summed in ascending order and the segment sums are
+// added in segment order, so the result depends only on p and the row count.
+// seg is LDS scratch of blockDim.x entries that must not alias dst.  Every
+// thread must call it.
+__device__ inline void red_load(const Red r, z64* dst, int p, z64* seg) {
+  const int E = p * p, t = threadIdx.x;
+  const int nseg = max(1, min((int)blockDim.x / E, r.nrows));
+  const int chunk = (r.nrows + nseg - 1) / nseg;
+  const int sg = t / E, e = t % E;
+  if (nseg == 1) {
+    if (t < E) dst[e] = red_rows(r, e, 0, r.nrows);
+    return;
   }
-  for (; k < r.nrows; ++k) s += r.base[(size_t)k * r.ld + r.off];
+  if (sg < nseg) seg[sg * E + e] = red_rows(r, e, min(r.nrows, sg * chunk), min(r.nrows, (sg + 1) * chunk));
+  __syncthreads();
+  if (t < E) {
+    z64 acc = seg[e];
+    for (int k = 1; k < nseg; ++k) {
+      acc.re += seg[k * E + e].re;
+      acc.im += seg[k * E + e].im;
+    }
+    dst[e] = acc;
+  }
+  __syncthreads();  // seg may be reused
+}
+
+// Sum of one column of a reduced scalar, computed by a whole wave: lane l
+// sums a contiguous range of rows in ascending order, then the lanes combine
+// by a butterfly (every lane ends with the same value).  Every lane of the
+// calling wave must call it.
+__device__ inline double red_scalar(const Red r) {
+  const int l = threadIdx.x & 63;
+  const int chunk = (r.nrows + 63) / 64;
+  const int s0 = min(r.nrows, l * chunk), s1 = min(r.nrows, s0 + chunk);
+  double s = 0.0;
+  for (int k = s0; k < s1; ++k) s += r.base[(size_t)k * r.ld + r.off];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
   return s;
 }
 
@@ -163,7 +193,7 @@ __device__ inline double max_abs(const z64* M, int p, double* sh) {
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
   double r = sh[0];
-  for (int w = 1; w < PXW; ++w) r = fmax(r, sh[w]);
+  for (int w = 1; w < px_waves(); ++w) r = fmax(r, sh[w]);
   __syncthreads();
   return r;
 }
@@ -175,7 +205,7 @@ __device__ inline double sum_all(double v, double* sh) {
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
   double r = 0.0;
-  for (int w = 0; w < PXW; ++w) r += sh[w];
+  for (int w = 0; w < px_waves(); ++w) r += sh[w];
   __syncthreads();
   return r;
 }
@@ -259,7 +289,7 @@ __global__ __launch_bounds__(PXT) void k_chol(CholArgs a) {
   __shared__ double sh[PXW];
   const int p = st->p;
   z64* slots = a.slots;
-  red_load(a.g, G, p);
+  red_load(a.g, G, p, T1);
   __syncthreads();
   double dmax = 0.0;
   for (int i = 0; i < p; ++i) dmax = fmax(dmax, G[i * p + i].re);
@@ -273,7 +303,7 @@ __global__ __launch_bounds__(PXT) void k_chol(CholArgs a) {
     double r2 = 0.0;
     if (a.mode == 1) {
       // tr(xi^H G xi) = sum_ij conj(xi_ij) (G xi)_ij  (xi = I at start-up)
-      for (int e = threadIdx.x; e < p * p; e += PXT) {
+      for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
         const int i = e / p, j = e % p;
         if (a.init) {
           if (i == j) r2 += G[e].re;
@@ -285,7 +315,7 @@ __global__ __launch_bounds__(PXT) void k_chol(CholArgs a) {
       }
     } else {
       const z64* R1 = slots + S_R1 * SLOT;
-      for (int e = threadIdx.x; e < p * p; e += PXT) {
+      for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
         const int i = e / p, j = e % p;
         z64 t = czero<double>();
         for (int k = 0; k < p; ++k) cfma(t, R1[i * p + k], a.init ? (k == j ? z64{1, 0} : z64{0, 0}) : xi[k * p + j]);
@@ -325,7 +355,7 @@ __global__ __launch_bounds__(PXT) void k_chol(CholArgs a) {
     mm<false>(T2, G, R, p);
   __syncthreads();
   double n2 = 0.0;
-  for (int e = threadIdx.x; e < p * p; e += PXT) n2 += cabs2(R[e]);
+  for (int e = threadIdx.x; e < p * p; e += blockDim.x) n2 += cabs2(R[e]);
   n2 = sum_all(n2, sh);
   copy_pp(R, slots + S_XI * SLOT, p);
   if (threadIdx.x == 0) {
@@ -374,8 +404,9 @@ __global__ __launch_bounds__(PXT) void k_solve(SolveArgs a) {
   __shared__ double sh[PXW];
   const int p = st->p;
   z64* slots = a.slots;
+  const double nsum = (a.nred.base != nullptr) ? red_scalar(a.nred) : 0.0;
   if (a.nred.base != nullptr && threadIdx.x == 0) {
-    const double r = sqrt(fmax(red_scalar(a.nred), 0.0)) / st->normB;
+    const double r = sqrt(fmax(nsum, 0.0)) / st->normB;
     a.hist[a.hist_idx] = r;
     if (!(r == r) || isinf(r) || r > st->div_limit) {
       st->stop_iter = a.hist_idx;
@@ -390,11 +421,11 @@ __global__ __launch_bounds__(PXT) void k_solve(SolveArgs a) {
   }
   // every slot is read before save_slot (which may be mslot) is written
   if (a.mred.base != nullptr)
-    red_load(a.mred, M, p);
+    red_load(a.mred, M, p, X);
   else
     copy_pp(slots + a.mslot * SLOT, M, p);
   if (a.rred.base != nullptr)
-    red_load(a.rred, Rh, p);
+    red_load(a.rred, Rh, p, X);
   else
     copy_pp(slots + a.rslot * SLOT, Rh, p);
   if (a.rhs_tauT) copy_pp(slots + S_TAU * SLOT, T, p);
@@ -412,7 +443,7 @@ __global__ __launch_bounds__(PXT) void k_solve(SolveArgs a) {
   bool finite = ok;
   if (ok) {
     double chk = 0.0;
-    for (int e = threadIdx.x; e < p * p; e += PXT) chk += Rh[e].re + Rh[e].im;
+    for (int e = threadIdx.x; e < p * p; e += blockDim.x) chk += Rh[e].re + Rh[e].im;
     chk = sum_all(chk * 0.0, sh);  // NaN/Inf anywhere propagates
     finite = (chk == 0.0);
   }
@@ -433,10 +464,12 @@ __global__ __launch_bounds__(PXT) void k_solve(SolveArgs a) {
 // variants, hist[0] = sqrt(sum nred) / ||B|| with the stop test (if nred is).
 __global__ __launch_bounds__(PXT) void k_start(Red nred, Red gred, int slot, z64* slots, double* hist,
                                               DevState* st) {
+  __shared__ z64 seg[SLOT];
   const int p = st->p;
-  if (gred.base != nullptr) red_load(gred, slots + slot * SLOT, p);
+  if (gred.base != nullptr) red_load(gred, slots + slot * SLOT, p, seg);
+  const double nsum = (nred.base != nullptr) ? red_scalar(nred) : 0.0;
   if (nred.base != nullptr && threadIdx.x == 0) {
-    const double r = sqrt(fmax(red_scalar(nred), 0.0)) / st->normB;
+    const double r = sqrt(fmax(nsum, 0.0)) / st->normB;
     hist[0] = r;
     if (!(r == r) || isinf(r)) {
       st->stop_iter = 0;
@@ -467,7 +500,8 @@ __global__ void k_state_init(DevState* st, int p, int maxit, double tol, double 
 
 // normB = sqrt(sum nred).
 __global__ void k_set_norm(DevState* st, Red nred) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) st->normB = sqrt(fmax(red_scalar(nred), 0.0));
+  const double s = red_scalar(nred);  // launched as one wave
+  if (threadIdx.x == 0 && blockIdx.x == 0) st->normB = sqrt(fmax(s, 0.0));
 }
 
 }  // namespace blk

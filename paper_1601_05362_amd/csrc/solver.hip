@@ -343,13 +343,13 @@ static void solve_pp(Ctx& c, SolveArgs a) {
   a.slots = c.slots;
   a.hist = c.hist;
   a.st = c.st;
-  k_solve<<<1, PXT, 0, c.s>>>(a);
+  k_solve<<<1, px_threads(c.p), 0, c.s>>>(a);
   LAUNCH_CHECK();
 }
 
 static void chol_pp(Ctx& c, Red g, int mode, int gate, int idx, int init) {
   CholArgs a{g, mode, gate, idx, init, c.slots, c.hist, c.st};
-  k_chol<<<1, PXT, 0, c.s>>>(a);
+  k_chol<<<1, px_threads(c.p), 0, c.s>>>(a);
   LAUNCH_CHECK();
 }
 
@@ -478,10 +478,10 @@ static SolveOut run_solve(Ctx& c, const DevOp<T>& Aop, bool cocr, bool rq, const
       Red gqv = finish(c, RO_S, E2, 0, 0);
       copy_block<T, T>(c, V, p, U, p, 1.0, 0);
       gram<T, A, G_UNCONJ, false>(c, U, p, U, p, RO_B, 0);
-      k_start<<<1, PXT, 0, c.s>>>(no_red(), gqv, S_GOLD, c.slots, c.hist, c.st);
+      k_start<<<1, px_threads(c.p), 0, c.s>>>(no_red(), gqv, S_GOLD, c.slots, c.hist, c.st);
       LAUNCH_CHECK();
     } else {
-      k_start<<<1, PXT, 0, c.s>>>(no_red(), gqq, S_GOLD, c.slots, c.hist, c.st);
+      k_start<<<1, px_threads(c.p), 0, c.s>>>(no_red(), gqq, S_GOLD, c.slots, c.hist, c.st);
       LAUNCH_CHECK();
     }
     h = read_state(c);
@@ -566,13 +566,13 @@ static SolveOut run_solve(Ctx& c, const DevOp<T>& Aop, bool cocr, bool rq, const
       Red grv = finish(c, RO_S, E2, 0, -1);
       copy_block<T, T>(c, V, p, U, p, 1.0, -1);
       gram<T, A, G_UNCONJ, false>(c, U, p, U, p, RO_B, -1);
-      k_start<<<1, PXT, 0, c.s>>>(nr, grv, S_GOLD, c.slots, c.hist, c.st);
+      k_start<<<1, px_threads(c.p), 0, c.s>>>(nr, grv, S_GOLD, c.slots, c.hist, c.st);
       LAUNCH_CHECK();
     } else {
       Red gr = gram<T, A, G_UNCONJ, true>(c, R, p, R, p, RO_A, -1);
       Red nr = gr;
       nr.off = E2;
-      k_start<<<1, PXT, 0, c.s>>>(nr, gr, S_GOLD, c.slots, c.hist, c.st);
+      k_start<<<1, px_threads(c.p), 0, c.s>>>(nr, gr, S_GOLD, c.slots, c.hist, c.st);
       LAUNCH_CHECK();
     }
     h = read_state(c);
