@@ -45,10 +45,16 @@ __device__ inline double block_sum(double v, double* sh) {
 
 // Per-block accumulator of G = Y^T Z (CONJ = false) or Y^H Z (CONJ = true)
 // over rows staged in LDS tiles ys/zs of RPB x PP entries.  Accumulates in A.
+// PP >= 16: thread t owns entries t, t + NT, ... and sums every row of a
+// tile.  PP < 16 (fewer entries than threads): the tile's rows are split into
+// NG = NT / PP^2 groups of PP rows, thread t owns entry t % PP^2 of group
+// t / PP^2, and store() adds the groups in group order.
 template <typename T, typename A, int PP, bool CONJ>
 struct GramAcc {
   static constexpr int RPB = NT / PP;
   static constexpr int NE = (PP * PP + NT - 1) / NT;
+  static constexpr int NG = PP * PP >= NT ? 1 : NT / (PP * PP);
+  static_assert(NG == 1 || RPB == NG * PP, "row groups tile the rows");
   cx<A> acc[NE];
 
   __device__ void zero() {
@@ -56,33 +62,67 @@ struct GramAcc {
     for (int q = 0; q < NE; ++q) acc[q] = czero<A>();
   }
   __device__ void add(const cx<T>* ys, const cx<T>* zs) {
+    if constexpr (NG > 1) {
+      const int e = threadIdx.x % (PP * PP), r0 = (threadIdx.x / (PP * PP)) * PP;
+      const int i = e / PP, j = e % PP;
 #pragma unroll
-    for (int q = 0; q < NE; ++q) {
-      const int e = threadIdx.x + q * NT;
-      if (e < PP * PP) {
-        const int i = e / PP, j = e % PP;
+      for (int r = r0; r < r0 + PP; ++r) {
+        const cx<A> a = ccast<A>(ys[r * PP + i]);
+        const cx<A> b = ccast<A>(zs[r * PP + j]);
+        if (CONJ)
+          cfma_conj(acc[0], a, b);
+        else
+          cfma(acc[0], a, b);
+      }
+    } else {
 #pragma unroll
-        for (int r = 0; r < RPB; ++r) {
-          const cx<A> a = ccast<A>(ys[r * PP + i]);
-          const cx<A> b = ccast<A>(zs[r * PP + j]);
-          if (CONJ)
-            cfma_conj(acc[q], a, b);
-          else
-            cfma(acc[q], a, b);
+      for (int q = 0; q < NE; ++q) {
+        const int e = threadIdx.x + q * NT;
+        if (e < PP * PP) {
+          const int i = e / PP, j = e % PP;
+#pragma unroll
+          for (int r = 0; r < RPB; ++r) {
+            const cx<A> a = ccast<A>(ys[r * PP + i]);
+            const cx<A> b = ccast<A>(zs[r * PP + j]);
+            if (CONJ)
+              cfma_conj(acc[q], a, b);
+            else
+              cfma(acc[q], a, b);
+          }
         }
       }
     }
   }
   // Write the p x p block partial (row-major, ld p) as doubles at dst.
+  // Every thread must call it.
   __device__ void store(double* dst, int p) const {
-#pragma unroll
-    for (int q = 0; q < NE; ++q) {
-      const int e = threadIdx.x + q * NT;
+    if constexpr (NG > 1) {
+      __shared__ cx<A> gs[NT];
+      gs[threadIdx.x] = acc[0];
+      __syncthreads();
+      const int e = threadIdx.x;
       if (e < PP * PP) {
+        cx<A> v = gs[e];
+        for (int g = 1; g < NG; ++g) {
+          v.re += gs[g * PP * PP + e].re;
+          v.im += gs[g * PP * PP + e].im;
+        }
         const int i = e / PP, j = e % PP;
         if (i < p && j < p) {
-          dst[2 * (i * p + j)] = (double)acc[q].re;
-          dst[2 * (i * p + j) + 1] = (double)acc[q].im;
+          dst[2 * (i * p + j)] = (double)v.re;
+          dst[2 * (i * p + j) + 1] = (double)v.im;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < NE; ++q) {
+        const int e = threadIdx.x + q * NT;
+        if (e < PP * PP) {
+          const int i = e / PP, j = e % PP;
+          if (i < p && j < p) {
+            dst[2 * (i * p + j)] = (double)acc[q].re;
+            dst[2 * (i * p + j) + 1] = (double)acc[q].im;
+          }
         }
       }
     }
