@@ -40,9 +40,12 @@ def spmm_bytes(n: int, nnz: int, p: int, cbytes: int, colind: bool = True) -> in
 
 
 # the kernel and the host code that picks its launch shape
+# What the standalone product's counters depend on: the kernel sources and the
+# launch code (apply_op, a region of solver.hip).
 SPMM_SOURCES = ["paper_1601_05362_amd/csrc/spmm.hpp", "paper_1601_05362_amd/csrc/grid.hpp",
-                "paper_1601_05362_amd/csrc/rowpass.hpp", "paper_1601_05362_amd/csrc/common.hpp",
-                "paper_1601_05362_amd/csrc/solver.hip"]
+                "paper_1601_05362_amd/csrc/common.hpp",
+                ("paper_1601_05362_amd/csrc/solver.hip", "// Y = A Z (SUB: Y = C - A Z)",
+                 "template <typename T>\nstatic void zero_block")]
 TRAFFIC_PROFILE = "profiles/k_spmm_c128_p32_helmholtz3d_128.md"
 
 
@@ -50,9 +53,14 @@ def source_hash(paths) -> str:
     import hashlib
 
     h = hashlib.sha256()
-    for rel in paths:
+    for item in paths:
+        rel, begin, end = item if isinstance(item, tuple) else (item, None, None)
         with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+            data = f.read()
+        if begin is not None:
+            i = data.index(begin.encode())
+            data = data[i:data.index(end.encode(), i)]
+        h.update(data)
     return h.hexdigest()[:16]
 
 
