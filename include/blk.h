@@ -197,6 +197,19 @@ int32_t blk_spmm_c(int64_t n, int64_t nnz, const int32_t *rowptr, const int32_t 
                    int64_t ldy, void *stream);
 
 /*
+ * The block product of a dense operator in complex64 (the Green's-function
+ * matrices of the paper's second experiment, as the inner solves of the
+ * mixed-precision form use them): Y = A Z with A row-major n x n (element
+ * (i, k) at A[i*lda + k], lda >= n), Z and Y n x p (ld >= p).  FP32
+ * accumulation; at p > 16 on the FP32 matrix cores.  Y must not overlap Z.
+ * At p > 16 the call allocates a split-K workspace (4 n 32 complex128-sized
+ * entries) and returns when the product is done; otherwise it allocates
+ * nothing and does not wait.  Returns BLK_OK or an error.
+ */
+int32_t blk_dense_c(int64_t n, const blk_c *A, int64_t lda, int64_t p, const blk_c *Z, int64_t ldz,
+                    blk_c *Y, int64_t ldy, void *stream);
+
+/*
  * p x p bilinear form of two n x p blocks, complex128, written [host]
  * row-major to G: G = Y^T Z (conj = 0, the unconjugated form of Table 1)
  * or G = Y^H Z (conj = 1).

@@ -41,6 +41,7 @@ __all__ = [
     "blk_op_analyze",
     "blk_spmm_z",
     "blk_spmm_c",
+    "blk_dense_c",
     "blk_gram_z",
     "blk_thin_qr_z",
     "blk_last_error",
@@ -255,6 +256,26 @@ def blk_spmm_c(A: CsrOperator, Z: torch.Tensor, out=None):
                             _ptr(Z), ldz, _ptr(Y), ldy, _stream(Z.device))
     if rc != 0:
         _raise(rc, "blk_spmm_c")
+    return Y
+
+
+def blk_dense_c(A: torch.Tensor, Z: torch.Tensor, out=None):
+    """complex64 Y = A Z for a dense row-major complex64 A (FP32 accumulation;
+    FP32 matrix cores at p > 16)."""
+    lib = _lib()
+    if A.dtype != torch.complex64 or A.dim() != 2 or A.shape[0] != A.shape[1] or A.stride(1) != 1:
+        raise ValueError("A must be a square row-major complex64 tensor")
+    ldz = _block(Z, "Z", torch.complex64)
+    n, p = Z.shape
+    if A.shape[0] != n:
+        raise ValueError("A and Z sizes differ")
+    Y = out if out is not None else torch.empty((n, p), dtype=torch.complex64, device=Z.device)
+    ldy = _block(Y, "out", torch.complex64)
+    with torch.cuda.device(Z.device):
+        rc = lib.blk_dense_c(n, A.data_ptr(), A.stride(0), p, _ptr(Z), ldz, _ptr(Y), ldy,
+                             _stream(Z.device))
+    if rc != 0:
+        _raise(rc, "blk_dense_c")
     return Y
 
 

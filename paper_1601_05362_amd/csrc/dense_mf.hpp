@@ -1,5 +1,6 @@
 // Dense operator application Y = A Z (the Green's-function matrices of the
-// paper's second experiment) on the FP64 matrix cores, complex128, p <= 32.
+// paper's second experiment) on the matrix cores, p <= 32: complex128 on the
+// FP64 instruction (k_dense_mf), complex64 on the FP32 one (k_dense_mf32).
 //
 // A is row-major n x n.  A workgroup of four waves owns 64 rows (16 per wave)
 // and one of DSPLIT contiguous ranges of the columns of A (split K); it
@@ -85,12 +86,95 @@ __global__ __launch_bounds__(NT, 2) void k_dense_mf(int64_t n, const z64* __rest
     }
 }
 
+// The complex64 product (the inner solves of the mixed-precision form) on the
+// FP32 matrix cores, v_mfma_f32_16x16x4f32 with FP32 accumulation, in the
+// same tiling as k_dense_mf.  Its D layout differs from the FP64
+// instruction's: register v of lane l holds row 4 (l / 16) + v.  Each lane
+// loads two consecutive complex entries of A (16 bytes) per pair of k-steps,
+// so the k index of step s for lane group m = l / 16 is
+// 8 (s / 2) + 2 m + s % 2, and the staged Z is read with the same index.
+typedef float f4 __attribute__((ext_vector_type(4)));
+__device__ inline f4 mfma32(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+struct __attribute__((aligned(8))) c32x2 {
+  float r0, i0, r1, i1;
+};
+
+// part: DSPLIT x n x 32 complex64 partial products (columns >= p are zero).
+__global__ __launch_bounds__(NT, 2) void k_dense_mf32(int64_t n, const c32* __restrict__ A, int64_t lda,
+                                                      const c32* __restrict__ Z, int ldz, int p,
+                                                      c32* __restrict__ part, const DevState* st,
+                                                      int gate) {
+  if (st && gate >= st->stop_iter) return;
+  __shared__ c32 zs[DKC * 32];
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6, m = l >> 4;
+  const int64_t rb = blockIdx.x / DSPLIT;
+  const int sp = blockIdx.x % DSPLIT;
+  const int64_t kper = ((n + DSPLIT - 1) / DSPLIT + DKC - 1) / DKC * DKC;
+  const int64_t kb = sp * kper, ke = kb + kper < n ? kb + kper : n;
+  const int64_t row = rb * DROWS + 16 * w + (l & 15);  // A-layout row of this lane
+  const bool rok = row < n;
+  f4 cr[2], ci[2];
+#pragma unroll
+  for (int jb = 0; jb < 2; ++jb) cr[jb] = ci[jb] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int64_t k0 = kb; k0 < ke; k0 += DKC) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < DKC * 32 / NT; ++u) {
+      const int e = threadIdx.x + u * NT;
+      const int64_t k = k0 + e / 32;
+      const int col = e % 32;
+      zs[e] = (k < ke && col < p) ? Z[k * ldz + col] : czero<float>();
+    }
+    float ar[DKC / 4], ai[DKC / 4];
+#pragma unroll
+    for (int t = 0; t < DKC / 8; ++t) {
+      const int64_t k = k0 + 8 * t + 2 * m;
+      if (rok && k + 1 < ke) {
+        const c32x2 a = *reinterpret_cast<const c32x2*>(A + row * lda + k);
+        ar[2 * t] = a.r0;
+        ai[2 * t] = a.i0;
+        ar[2 * t + 1] = a.r1;
+        ai[2 * t + 1] = a.i1;
+      } else {
+        const c32 a0 = (rok && k < ke) ? A[row * lda + k] : czero<float>();
+        ar[2 * t] = a0.re;
+        ai[2 * t] = a0.im;
+        ar[2 * t + 1] = 0.f;
+        ai[2 * t + 1] = 0.f;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < DKC / 4; ++s) {
+      const int kk = 8 * (s >> 1) + 2 * m + (s & 1);
+#pragma unroll
+      for (int jb = 0; jb < 2; ++jb) {
+        const c32 b = zs[kk * 32 + 16 * jb + (l & 15)];
+        cr[jb] = mfma32(ar[s], b.re, cr[jb]);
+        cr[jb] = mfma32(-ai[s], b.im, cr[jb]);
+        ci[jb] = mfma32(ar[s], b.im, ci[jb]);
+        ci[jb] = mfma32(ai[s], b.re, ci[jb]);
+      }
+    }
+  }
+  c32* dst = part + (size_t)sp * n * 32;
+#pragma unroll
+  for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t r = rb * DROWS + 16 * w + 4 * m + v;
+      if (r < n) dst[r * 32 + 16 * jb + (l & 15)] = c32{cr[jb][v], ci[jb][v]};
+    }
+}
+
 // Y = sum of the DSPLIT partials in split order (SUB: Y = C - sum), stored
 // if STORE; NORM: ||Y||_F^2 partial of this block at part[blockIdx.x * E + E - 1].
-template <bool SUB, bool STORE, bool NORM>
-__global__ __launch_bounds__(NT) void k_dense_fin(int64_t n, int p, const z64* __restrict__ ws,
-                                                  const z64* __restrict__ Cm, int ldc,
-                                                  z64* __restrict__ Y, int ldy, double* part, int E,
+template <typename T, bool SUB, bool STORE, bool NORM>
+__global__ __launch_bounds__(NT) void k_dense_fin(int64_t n, int p, const cx<T>* __restrict__ ws,
+                                                  const cx<T>* __restrict__ Cm, int ldc,
+                                                  cx<T>* __restrict__ Y, int ldy, double* part, int E,
                                                   const DevState* st, int gate) {
   if (st && gate >= st->stop_iter) return;
   __shared__ double sh[NT / 64];
@@ -99,16 +183,16 @@ __global__ __launch_bounds__(NT) void k_dense_fin(int64_t n, int p, const z64* _
     const int64_t r = e / 32;
     const int col = (int)(e % 32);
     if (col >= p) continue;
-    z64 y = ws[e];
+    cx<T> y = ws[e];
 #pragma unroll
     for (int sp = 1; sp < DSPLIT; ++sp) {
-      const z64 v = ws[(size_t)sp * n * 32 + e];
+      const cx<T> v = ws[(size_t)sp * n * 32 + e];
       y.re += v.re;
       y.im += v.im;
     }
     if (SUB) y = csub(Cm[r * ldc + col], y);
     if (STORE) Y[r * ldy + col] = y;
-    if (NORM) nrm += cabs2(y);
+    if (NORM) nrm += (double)cabs2(y);
   }
   if (NORM) {
     const double s = block_sum(nrm, sh);

@@ -243,13 +243,39 @@ static void apply_op(Ctx& c, const DevOp<T>& A, const cx<T>* Z, int ldz, const c
           k_dense_mf<<<(unsigned)dense_blocks(c.n), NT, 0, c.s>>>(c.n, Ad, A.ld, Zd, ldz, c.p, c.dws,
                                                                   st, gate);
           LAUNCH_CHECK();
-          k_dense_fin<SUB, STORE, NORM><<<c.G, NT, 0, c.s>>>(c.n, c.p, c.dws, Cd, ldc, Yd, ldy, part,
-                                                             E, st, gate);
+          k_dense_fin<double, SUB, STORE, NORM><<<c.G, NT, 0, c.s>>>(c.n, c.p, c.dws, Cd, ldc, Yd, ldy,
+                                                                     part, E, st, gate);
           LAUNCH_CHECK();
           if (GRAM) {
             static_assert(!GRAM || STORE, "the Gram of a dense product reads the stored Y");
             k_gram_mf<2, G_UNCONJ, false><<<c.G, NT, 0, c.s>>>(c.n, c.p, Zd, ldz, Yd, ldy, part, E, st,
                                                                gate);
+          }
+          LAUNCH_CHECK();
+          return;
+        }
+      }
+      if constexpr (std::is_same<T, float>::value && PP == 32) {
+        if (c.dws) {
+          // complex64 (the mixed form's inner solves): FP32 matrix cores into
+          // split-K partials held in the same workspace, their fixed-order sum
+          // with the epilogues, then the Gram Z^T Y with FP64 accumulation
+          // from the stored Y (the casts only name T = float)
+          const c32* Af = reinterpret_cast<const c32*>(A.dense);
+          const c32* Zf = reinterpret_cast<const c32*>(Z);
+          const c32* Cf = reinterpret_cast<const c32*>(C);
+          c32* Yf = reinterpret_cast<c32*>(Y);
+          c32* ws = reinterpret_cast<c32*>(c.dws);
+          k_dense_mf32<<<(unsigned)dense_blocks(c.n), NT, 0, c.s>>>(c.n, Af, A.ld, Zf, ldz, c.p, ws, st,
+                                                                    gate);
+          LAUNCH_CHECK();
+          k_dense_fin<float, SUB, STORE, NORM><<<c.G, NT, 0, c.s>>>(c.n, c.p, ws, Cf, ldc, Yf, ldy, part,
+                                                                    E, st, gate);
+          LAUNCH_CHECK();
+          if (GRAM) {
+            static_assert(!GRAM || STORE, "the Gram of a dense product reads the stored Y");
+            k_gram<float, double, 32, G_UNCONJ, false><<<c.G, NT, 0, c.s>>>(c.n, c.p, Zf, ldz, Yf, ldy,
+                                                                            part, E, st, gate);
           }
           LAUNCH_CHECK();
           return;
@@ -1146,6 +1172,39 @@ int32_t blk_spmm_c(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t*
     apply_op<float, false, true, false, false>(c, A32, reinterpret_cast<const c32*>(Z), (int)ldz,
                                                nullptr, 0, reinterpret_cast<c32*>(Y), (int)ldy,
                                                RO_S, 0, -1);
+    return BLK_OK;
+  } catch (const HipError& e) {
+    if (e.e == hipErrorOutOfMemory) return fail(BLK_ENOMEM, "%s: %s", e.what, hipGetErrorString(e.e));
+    return fail(BLK_EHIP, "%s: %s", e.what, hipGetErrorString(e.e));
+  }
+}
+
+int32_t blk_dense_c(int64_t n, const blk_c* A, int64_t lda, int64_t p, const blk_c* Z, int64_t ldz,
+                    blk_c* Y, int64_t ldy, void* stream) {
+  g_err.clear();
+  if (n < 1 || n > (int64_t)0x7fffffff) return fail(BLK_EINVAL, "bad n");
+  if (!A || !Z || !Y) return fail(BLK_EINVAL, "NULL pointer");
+  if (lda < n) return fail(BLK_EINVAL, "dense ld < n");
+  if (p < 1 || p > BLK_MAX_P) return fail(BLK_EINVAL, "p outside 1..%d", BLK_MAX_P);
+  if (ldz < p || ldy < p) return fail(BLK_EINVAL, "leading dimension < p");
+  if (overlaps(Y, sizeof(blk_c) * ((n - 1) * ldy + p), Z, sizeof(blk_c) * ((n - 1) * ldz + p)))
+    return fail(BLK_EINVAL, "Y overlaps Z");
+  hipStream_t s = (hipStream_t)stream;
+  try {
+    Pool pool;
+    Ctx c;
+    ctx_geometry(c, n, (int)p, s);
+    // p > 16: the matrix-core product needs the split-K partials
+    if (p > 16) c.dws = pool.get<z64>(sizeof(z64) * (size_t)DSPLIT * n * 32);
+    DevOp<float> A32;
+    A32.kind = BLK_OP_DENSE;
+    A32.n = n;
+    A32.dense = reinterpret_cast<const c32*>(A);
+    A32.ld = lda;
+    apply_op<float, false, true, false, false>(c, A32, reinterpret_cast<const c32*>(Z), (int)ldz,
+                                               nullptr, 0, reinterpret_cast<c32*>(Y), (int)ldy,
+                                               RO_S, 0, -1);
+    if (c.dws) HIPCHK(hipStreamSynchronize(s));  // before the workspace is freed
     return BLK_OK;
   } catch (const HipError& e) {
     if (e.e == hipErrorOutOfMemory) return fail(BLK_ENOMEM, "%s: %s", e.what, hipGetErrorString(e.e));

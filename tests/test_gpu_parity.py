@@ -550,6 +550,32 @@ def test_dense_mfma_apply_matches_oracle(pkg, dev, n, p):
     assert np.max(np.abs(Y3 - (Cm - ref))) <= 1e-13 * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("n,p", [(1000, 32), (1024, 20), (77, 17), (333, 8)])
+def test_dense_c64_product_within_fp32_bound(pkg, dev, n, p):
+    """The complex64 dense product (FP32 matrix cores at p > 16, the vector
+    kernel below) against the oracle's FP64 product of the same complex64
+    inputs.  The real (imaginary) part of an entry is a sum of 2n real
+    products taken in FP32 in some order (split K, matrix-core blocks), so its
+    error is at most gamma_{2n} sum_k |a_ik| |z_kj| (|ar zr| + |ai zi| <=
+    |a| |z|), gamma_m = m u / (1 - m u), u = 2^-24; the modulus error is at
+    most sqrt(2) times that.  The test asserts this bound, and that the
+    typical error is near sqrt(n) u, far below it.  Ragged row blocks and K
+    ranges (n = 77, 333, 1000), odd lda, padded columns."""
+    k = 2 * math.pi * 1.5
+    A = W.greens_sphere(n, k).astype(np.complex64)
+    Z = W.cgauss(n, p, seed=14).astype(np.complex64)
+    ref = O.apply(A.astype(np.complex128), Z.astype(np.complex128))
+    Y = pkg.blk_dense_c(torch.as_tensor(A, device=dev), torch.as_tensor(Z, device=dev)).cpu().numpy()
+    u = 2.0 ** -24
+    m = 2 * n
+    gamma = m * u / (1 - m * u)
+    absprod = np.abs(A).astype(np.float64) @ np.abs(Z).astype(np.float64)
+    err = np.abs(Y.astype(np.complex128) - ref)
+    assert np.all(err <= math.sqrt(2) * gamma * absprod), float(np.max(err / (gamma * absprod)))
+    rel = np.linalg.norm(Y.astype(np.complex128) - ref) / np.linalg.norm(ref)
+    assert rel < 50 * math.sqrt(n) * u, rel
+
+
 def test_dense_mfma_solver_parity(pkg, dev):
     """Block COCR_rq on a dense Green's operator at p = 32 against the oracle."""
     n, p = 1024, 32
