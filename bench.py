@@ -39,13 +39,11 @@ def spmm_bytes(n: int, nnz: int, p: int, cbytes: int, colind: bool = True) -> in
     return nnz * (cbytes + (4 if colind else 0)) + 4 * (n + 1) + 2 * n * p * cbytes
 
 
-# the kernel and the host code that picks its launch shape
-# What the standalone product's counters depend on: the kernel sources and the
-# launch code (apply_op, a region of solver.hip).
-SPMM_SOURCES = ["paper_1601_05362_amd/csrc/spmm.hpp", "paper_1601_05362_amd/csrc/grid.hpp",
-                "paper_1601_05362_amd/csrc/common.hpp",
-                ("paper_1601_05362_amd/csrc/solver.hip", "// Y = A Z (SUB: Y = C - A Z)",
-                 "template <typename T>\nstatic void zero_block")]
+# What the standalone product's counters depend on: the 2.5D kernel's sources
+# and its launch code (the grid-stencil branch of apply_op in solver.hip).
+SPMM_SOURCES = ["paper_1601_05362_amd/csrc/grid.hpp", "paper_1601_05362_amd/csrc/common.hpp",
+                ("paper_1601_05362_amd/csrc/solver.hip", "        // grid-stencil pattern: 2.5D blocked product",
+                 "    if (A.kind == BLK_OP_CSR) {")]
 TRAFFIC_PROFILE = "profiles/k_spmm_c128_p32_helmholtz3d_128.md"
 
 
@@ -184,7 +182,7 @@ def main():
     b64 = spmm_bytes(A.n, A.nnz, p, 16, colind=not grid_path)
     Zc = Zd.to(torch.complex64)
     t_spmm32 = time_spmm(pkg, torch, Ad, Zc, args.spmm_reps, c64=True)
-    b32 = spmm_bytes(A.n, A.nnz, p, 8)
+    b32 = spmm_bytes(A.n, A.nnz, p, 8, colind=not grid_path)
     gbs64, gbs32 = b64 / t_spmm / 1e9, b32 / t_spmm32 / 1e9
     log(f"[bench] spmm c128 p={p}: {t_spmm * 1e3:.3f} ms, {gbs64:.0f} GB/s ({gbs64 / HBM_PEAK_GBS:.1%} of peak); "
         f"c64: {t_spmm32 * 1e3:.3f} ms, {gbs32:.0f} GB/s ({gbs32 / HBM_PEAK_GBS:.1%})")
@@ -228,13 +226,11 @@ def main():
                  "A_GBs": round(16.0 * nd * nd / (ms * 1e-3) / 1e9, 1)}
         log(f"[bench] dense c128 product n={nd} p={p}: {ms:.3f} ms, {tf:.1f} TFLOP/s")
         # the complex64 product of the mixed form's inner solves (FP32 matrix cores)
-        A32 = Dd.a.to(torch.complex64)
-        del Dd
         Z32, Y32 = Zd.to(torch.complex64), Yd.to(torch.complex64)
-        pkg.blk_dense_c(A32, Z32, out=Y32)
+        pkg.blk_spmm_c(Dd, Z32, out=Y32)
         e0.record(stream)
         for _ in range(5):
-            pkg.blk_dense_c(A32, Z32, out=Y32)
+            pkg.blk_spmm_c(Dd, Z32, out=Y32)
         e1.record(stream)
         torch.cuda.synchronize()
         ms32 = e0.elapsed_time(e1) / 5
@@ -243,7 +239,7 @@ def main():
                         "frac_fp32_peak": round(tf32 / 157.3, 4),
                         "A_GBs": round(8.0 * nd * nd / (ms32 * 1e-3) / 1e9, 1)}
         log(f"[bench] dense c64 product n={nd} p={p}: {ms32:.3f} ms, {tf32:.1f} TFLOP/s")
-        del A32, Z32, Y32, Zd, Yd
+        del Dd, Z32, Y32, Zd, Yd
         torch.cuda.synchronize()
 
     # --- solves -----------------------------------------------------------------

@@ -188,26 +188,21 @@ int32_t blk_spmm_z(const blk_op *A, int64_t p, const blk_z *Z, int64_t ldz, cons
 int32_t blk_op_analyze(blk_op *A, void *stream);
 
 /*
- * The same product in complex64 for a CSR operator whose values are given in
- * complex64 (val32[nnz]); accumulation is FP32.  Y = A Z.  Allocates
- * nothing and does not wait: the product is queued on `stream`.
+ * The block product of section 1 in complex64, as the mixed-precision form's
+ * inner solves use it: Y = A Z with A's pattern, kind and structure from *A and its
+ * values in complex64 from vals32 -- for CSR, vals32[nnz] in the order of
+ * colind; for DENSE, the row-major n x n matrix with leading dimension
+ * A->ld (A->val / A->dense are not read and may be NULL).  FP32
+ * accumulation; a DENSE operator at p > 16 runs on the FP32 matrix cores, a
+ * CSR operator marked BLK_STRUCT_GRID on the 2.5D stencil kernel (nothing is
+ * analysed here: BLK_STRUCT_UNKNOWN takes the general kernel).  Y must not
+ * overlap Z.  Allocates nothing and does not wait -- except for a DENSE
+ * operator with p > 16, whose product needs a split-K workspace (4 n 32
+ * complex128-sized entries): that call allocates it and returns when the
+ * product is done.  Returns BLK_OK or an error.
  */
-int32_t blk_spmm_c(int64_t n, int64_t nnz, const int32_t *rowptr, const int32_t *colind,
-                   const blk_c *val32, int64_t p, const blk_c *Z, int64_t ldz, blk_c *Y,
-                   int64_t ldy, void *stream);
-
-/*
- * The block product of a dense operator in complex64 (the Green's-function
- * matrices of the paper's second experiment, as the inner solves of the
- * mixed-precision form use them): Y = A Z with A row-major n x n (element
- * (i, k) at A[i*lda + k], lda >= n), Z and Y n x p (ld >= p).  FP32
- * accumulation; at p > 16 on the FP32 matrix cores.  Y must not overlap Z.
- * At p > 16 the call allocates a split-K workspace (4 n 32 complex128-sized
- * entries) and returns when the product is done; otherwise it allocates
- * nothing and does not wait.  Returns BLK_OK or an error.
- */
-int32_t blk_dense_c(int64_t n, const blk_c *A, int64_t lda, int64_t p, const blk_c *Z, int64_t ldz,
-                    blk_c *Y, int64_t ldy, void *stream);
+int32_t blk_spmm_c(const blk_op *A, const blk_c *vals32, int64_t p, const blk_c *Z, int64_t ldz,
+                   blk_c *Y, int64_t ldy, void *stream);
 
 /*
  * p x p bilinear form of two n x p blocks, complex128, written [host]

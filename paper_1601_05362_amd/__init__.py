@@ -41,7 +41,6 @@ __all__ = [
     "blk_op_analyze",
     "blk_spmm_z",
     "blk_spmm_c",
-    "blk_dense_c",
     "blk_gram_z",
     "blk_thin_qr_z",
     "blk_last_error",
@@ -150,6 +149,14 @@ class DenseOperator:
         self.a = a
         self.n = a.shape[0]
         self.device = a.device
+        self._val32 = None
+
+    @property
+    def val32(self) -> torch.Tensor:
+        """complex64 copy of the matrix (made on first use)."""
+        if self._val32 is None:
+            self._val32 = self.a.to(torch.complex64)
+        return self._val32
 
     def as_c(self) -> _capi.BlkOp:
         return _capi.BlkOp(BLK_OP_DENSE, _capi.BLK_STRUCT_GENERAL, self.n, 0, None, None, None,
@@ -243,39 +250,24 @@ def blk_spmm_z(A, Z: torch.Tensor, C_: torch.Tensor | None = None, out=None, gra
     return (Y, G) if gram else Y
 
 
-def blk_spmm_c(A: CsrOperator, Z: torch.Tensor, out=None):
-    """complex64 Y = A Z with FP32 accumulation (CSR only)."""
+def blk_spmm_c(A, Z: torch.Tensor, out=None):
+    """complex64 Y = A Z with FP32 accumulation, for a CsrOperator (its
+    complex64 values, grid structure if analysed) or a DenseOperator (its
+    complex64 copy)."""
     lib = _lib()
     ldz = _block(Z, "Z", torch.complex64)
     n, p = Z.shape
     Y = out if out is not None else torch.empty((n, p), dtype=torch.complex64, device=Z.device)
     ldy = _block(Y, "out", torch.complex64)
     v = A.val32
+    op = A.as_c()
+    if isinstance(A, DenseOperator):
+        op.ld = v.stride(0)
     with torch.cuda.device(Z.device):
-        rc = lib.blk_spmm_c(A.n, A.nnz, A.rowptr.data_ptr(), A.colind.data_ptr(), v.data_ptr(), p,
-                            _ptr(Z), ldz, _ptr(Y), ldy, _stream(Z.device))
+        rc = lib.blk_spmm_c(C.byref(op), v.data_ptr(), p, _ptr(Z), ldz, _ptr(Y), ldy,
+                            _stream(Z.device))
     if rc != 0:
         _raise(rc, "blk_spmm_c")
-    return Y
-
-
-def blk_dense_c(A: torch.Tensor, Z: torch.Tensor, out=None):
-    """complex64 Y = A Z for a dense row-major complex64 A (FP32 accumulation;
-    FP32 matrix cores at p > 16)."""
-    lib = _lib()
-    if A.dtype != torch.complex64 or A.dim() != 2 or A.shape[0] != A.shape[1] or A.stride(1) != 1:
-        raise ValueError("A must be a square row-major complex64 tensor")
-    ldz = _block(Z, "Z", torch.complex64)
-    n, p = Z.shape
-    if A.shape[0] != n:
-        raise ValueError("A and Z sizes differ")
-    Y = out if out is not None else torch.empty((n, p), dtype=torch.complex64, device=Z.device)
-    ldy = _block(Y, "out", torch.complex64)
-    with torch.cuda.device(Z.device):
-        rc = lib.blk_dense_c(n, A.data_ptr(), A.stride(0), p, _ptr(Z), ldz, _ptr(Y), ldy,
-                             _stream(Z.device))
-    if rc != 0:
-        _raise(rc, "blk_dense_c")
     return Y
 
 

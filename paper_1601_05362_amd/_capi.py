@@ -69,8 +69,7 @@ SIGNATURES = {
                               C.POINTER(BlkOpts), _P, _I64, _DP, _IP, _DP]),
     "blk_spmm_z": (_I32, [C.POINTER(BlkOp), _I64, _P, _I64, _P, _I64, _P, _I64, _P, _P]),
     "blk_op_analyze": (_I32, [C.POINTER(BlkOp), _P]),
-    "blk_spmm_c": (_I32, [_I64, _I64, _P, _P, _P, _I64, _P, _I64, _P, _I64, _P]),
-    "blk_dense_c": (_I32, [_I64, _P, _I64, _I64, _P, _I64, _P, _I64, _P]),
+    "blk_spmm_c": (_I32, [C.POINTER(BlkOp), _P, _I64, _P, _I64, _P, _I64, _P]),
     "blk_gram_z": (_I32, [_I64, _I64, _P, _I64, _P, _I64, _I32, _P, _P]),
     "blk_thin_qr_z": (_I32, [_I64, _I64, _P, _I64, _P, _I64, _P, _P]),
     "blk_last_error": (C.c_char_p, []),

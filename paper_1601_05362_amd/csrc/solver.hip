@@ -852,12 +852,13 @@ static bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
   return x < y + nb && y < x + na;
 }
 
-static int check_op(const blk_op* A) {
+// values = false: the complex128 values (val / dense) are not needed.
+static int check_op(const blk_op* A, bool values = true) {
   if (!A) return fail(BLK_EINVAL, "A is NULL");
   if (A->n < 1) return fail(BLK_EINVAL, "n = %lld < 1", (long long)A->n);
   if (A->n > (int64_t)0x7fffffff) return fail(BLK_EINVAL, "n too large for int32 indices");
   if (A->kind == BLK_OP_CSR) {
-    if (!A->rowptr || !A->colind || !A->val) return fail(BLK_EINVAL, "CSR pointer is NULL");
+    if (!A->rowptr || !A->colind || (values && !A->val)) return fail(BLK_EINVAL, "CSR pointer is NULL");
     if (A->nnz < 0 || A->nnz > (int64_t)0x7fffffff) return fail(BLK_EINVAL, "bad nnz");
     if (A->structure < BLK_STRUCT_UNKNOWN || A->structure > BLK_STRUCT_GRID)
       return fail(BLK_EINVAL, "unknown structure %d", (int)A->structure);
@@ -866,7 +867,7 @@ static int check_op(const blk_op* A) {
          A->grid[1] > A->n || A->grid[2] > A->n || A->grid[0] * A->grid[1] * A->grid[2] != A->n))
       return fail(BLK_EINVAL, "grid dimensions do not match n");
   } else if (A->kind == BLK_OP_DENSE) {
-    if (!A->dense) return fail(BLK_EINVAL, "dense pointer is NULL");
+    if (values && !A->dense) return fail(BLK_EINVAL, "dense pointer is NULL");
     if (A->ld < A->n) return fail(BLK_EINVAL, "dense ld < n");
   } else {
     return fail(BLK_EINVAL, "unknown operator kind %d", (int)A->kind);
@@ -1148,45 +1149,16 @@ int32_t blk_spmm_z(const blk_op* A, int64_t p, const blk_z* Z, int64_t ldz, cons
   }
 }
 
-int32_t blk_spmm_c(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* colind,
-                   const blk_c* val32, int64_t p, const blk_c* Z, int64_t ldz, blk_c* Y, int64_t ldy,
-                   void* stream) {
+int32_t blk_spmm_c(const blk_op* A, const blk_c* vals32, int64_t p, const blk_c* Z, int64_t ldz,
+                   blk_c* Y, int64_t ldy, void* stream) {
   g_err.clear();
-  if (n < 1 || n > (int64_t)0x7fffffff) return fail(BLK_EINVAL, "bad n");
-  if (nnz < 0 || nnz > (int64_t)0x7fffffff) return fail(BLK_EINVAL, "bad nnz");
-  if (!rowptr || !colind || !val32 || !Z || !Y) return fail(BLK_EINVAL, "NULL pointer");
+  int rc = check_op(A, false);
+  if (rc) return rc;
+  if (!vals32) return fail(BLK_EINVAL, "vals32 is NULL");
   if (p < 1 || p > BLK_MAX_P) return fail(BLK_EINVAL, "p outside 1..%d", BLK_MAX_P);
+  if (!Z || !Y) return fail(BLK_EINVAL, "Z or Y is NULL");
   if (ldz < p || ldy < p) return fail(BLK_EINVAL, "leading dimension < p");
-  if (overlaps(Y, sizeof(blk_c) * ((n - 1) * ldy + p), Z, sizeof(blk_c) * ((n - 1) * ldz + p)))
-    return fail(BLK_EINVAL, "Y overlaps Z");
-  hipStream_t s = (hipStream_t)stream;
-  try {
-    Ctx c;
-    ctx_geometry(c, n, (int)p, s);
-    DevOp<float> A32;
-    A32.kind = BLK_OP_CSR;
-    A32.n = n;
-    A32.rowptr = rowptr;
-    A32.colind = colind;
-    A32.val = reinterpret_cast<const c32*>(val32);
-    apply_op<float, false, true, false, false>(c, A32, reinterpret_cast<const c32*>(Z), (int)ldz,
-                                               nullptr, 0, reinterpret_cast<c32*>(Y), (int)ldy,
-                                               RO_S, 0, -1);
-    return BLK_OK;
-  } catch (const HipError& e) {
-    if (e.e == hipErrorOutOfMemory) return fail(BLK_ENOMEM, "%s: %s", e.what, hipGetErrorString(e.e));
-    return fail(BLK_EHIP, "%s: %s", e.what, hipGetErrorString(e.e));
-  }
-}
-
-int32_t blk_dense_c(int64_t n, const blk_c* A, int64_t lda, int64_t p, const blk_c* Z, int64_t ldz,
-                    blk_c* Y, int64_t ldy, void* stream) {
-  g_err.clear();
-  if (n < 1 || n > (int64_t)0x7fffffff) return fail(BLK_EINVAL, "bad n");
-  if (!A || !Z || !Y) return fail(BLK_EINVAL, "NULL pointer");
-  if (lda < n) return fail(BLK_EINVAL, "dense ld < n");
-  if (p < 1 || p > BLK_MAX_P) return fail(BLK_EINVAL, "p outside 1..%d", BLK_MAX_P);
-  if (ldz < p || ldy < p) return fail(BLK_EINVAL, "leading dimension < p");
+  const int64_t n = A->n;
   if (overlaps(Y, sizeof(blk_c) * ((n - 1) * ldy + p), Z, sizeof(blk_c) * ((n - 1) * ldz + p)))
     return fail(BLK_EINVAL, "Y overlaps Z");
   hipStream_t s = (hipStream_t)stream;
@@ -1194,13 +1166,24 @@ int32_t blk_dense_c(int64_t n, const blk_c* A, int64_t lda, int64_t p, const blk
     Pool pool;
     Ctx c;
     ctx_geometry(c, n, (int)p, s);
-    // p > 16: the matrix-core product needs the split-K partials
-    if (p > 16) c.dws = pool.get<z64>(sizeof(z64) * (size_t)DSPLIT * n * 32);
     DevOp<float> A32;
-    A32.kind = BLK_OP_DENSE;
+    A32.kind = A->kind;
     A32.n = n;
-    A32.dense = reinterpret_cast<const c32*>(A);
-    A32.ld = lda;
+    if (A->kind == BLK_OP_CSR) {
+      A32.rowptr = A->rowptr;
+      A32.colind = A->colind;
+      A32.val = reinterpret_cast<const c32*>(vals32);
+      if (A->structure == BLK_STRUCT_GRID) {
+        A32.gnx = (int)A->grid[0];
+        A32.gny = (int)A->grid[1];
+        A32.gnz = (int)A->grid[2];
+      }
+    } else {
+      A32.dense = reinterpret_cast<const c32*>(vals32);
+      A32.ld = A->ld;
+      // p > 16: the matrix-core product needs the split-K partials
+      if (p > 16) c.dws = pool.get<z64>(sizeof(z64) * (size_t)DSPLIT * n * 32);
+    }
     apply_op<float, false, true, false, false>(c, A32, reinterpret_cast<const c32*>(Z), (int)ldz,
                                                nullptr, 0, reinterpret_cast<c32*>(Y), (int)ldy,
                                                RO_S, 0, -1);

@@ -80,7 +80,10 @@ def test_argument_validation_rejects_before_device_work():
     assert "ld" in lib.blk_last_error().decode()
     # kernels entry points
     assert lib.blk_gram_z(10, 0, fake, 1, fake, 1, 0, fake, None) == _capi.BLK_EINVAL
-    assert lib.blk_spmm_c(0, 0, fake, fake, fake, 1, fake, 1, fake + 4096, 1, None) == _capi.BLK_EINVAL
+    assert lib.blk_spmm_c(C.byref(op), None, 2, fake, 2, fake + 4096, 2, None) == _capi.BLK_EINVAL
+    assert "vals32" in lib.blk_last_error().decode()
+    assert lib.blk_spmm_c(C.byref(op), fake, 33, fake, 33, fake + 65536, 33, None) == _capi.BLK_EINVAL
+    assert lib.blk_spmm_c(None, fake, 2, fake, 2, fake + 4096, 2, None) == _capi.BLK_EINVAL
     assert lib.blk_thin_qr_z(10, 2, fake, 1, fake, 2, fake, None) == _capi.BLK_EINVAL
 
 

@@ -113,6 +113,31 @@ def test_spmm_c64_matches_oracle(pkg, dev, cfg1, p):
     assert np.max(np.abs(Y - ref)) <= 5 * 6e-8 * scale * 5
 
 
+@pytest.mark.parametrize("dims", [(13, 11, 9), (37, 29, 1), (16, 16, 33)])
+@pytest.mark.parametrize("p", [5, 8, 16, 17, 32])
+def test_spmm_c64_grid_within_fp32_bound(pkg, dev, dims, p):
+    """The complex64 product through the 2.5D stencil kernel (an analysed
+    operator) and the general kernel, against the FP64 product of the same
+    complex64 values: each part of an entry is a sum of at most 14 real
+    products in FP32, so its modulus error is at most sqrt(2) gamma_14
+    (|A| |Z|)_ij, u = 2^-24."""
+    A = W.grid_stencil_random(*dims, seed=5)
+    A.val = A.val.astype(np.complex64).astype(np.complex128)
+    Z = W.cgauss(A.n, p, seed=6).astype(np.complex64)
+    ref = O.apply(O.as_operator(A), Z.astype(np.complex128))
+    absA = O.as_operator(A).copy()
+    absA.data = np.abs(absA.data)
+    bound = math.sqrt(2) * (14 * 2.0 ** -24 / (1 - 14 * 2.0 ** -24)) * (absA @ np.abs(Z).astype(np.float64))
+    grd = pkg.CsrOperator.from_arrays(A.rowptr, A.colind, A.val, device=dev).analyze()
+    assert grd.structure == pkg._capi.BLK_STRUCT_GRID
+    gen = pkg.CsrOperator.from_arrays(A.rowptr, A.colind, A.val, device=dev)
+    gen.structure = pkg._capi.BLK_STRUCT_GENERAL
+    Zd = torch.as_tensor(Z, device=dev)
+    for op in (grd, gen):
+        Y = pkg.blk_spmm_c(op, Zd).cpu().numpy().astype(np.complex128)
+        assert np.all(np.abs(Y - ref) <= bound), float(np.max(np.abs(Y - ref) / np.maximum(bound, 1e-300)))
+
+
 @pytest.mark.parametrize("p", [1, 2, 7, 16, 32])
 @pytest.mark.parametrize("conj", [False, True])
 def test_gram_matches_oracle(pkg, dev, p, conj):
@@ -565,7 +590,9 @@ def test_dense_c64_product_within_fp32_bound(pkg, dev, n, p):
     A = W.greens_sphere(n, k).astype(np.complex64)
     Z = W.cgauss(n, p, seed=14).astype(np.complex64)
     ref = O.apply(A.astype(np.complex128), Z.astype(np.complex128))
-    Y = pkg.blk_dense_c(torch.as_tensor(A, device=dev), torch.as_tensor(Z, device=dev)).cpu().numpy()
+    # the operator's complex64 copy of these complex64-representable values is exact
+    Ad = pkg.DenseOperator(torch.as_tensor(A.astype(np.complex128), device=dev))
+    Y = pkg.blk_spmm_c(Ad, torch.as_tensor(Z, device=dev)).cpu().numpy()
     u = 2.0 ** -24
     m = 2 * n
     gamma = m * u / (1 - m * u)
