@@ -115,10 +115,13 @@ __global__ __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(8))) void k_
   constexpr int PL = W * H * PP;                   // plane + halo, in cx<T>
   constexpr int RS = (GTX * 7 + 31) / 32 * 32;     // coefficient slots per x-run
   static_assert(GTY * RS <= GT, "one coefficient per loader thread");
-  __shared__ __align__(16) cx<T> pl[PL];
-  __shared__ __align__(16) cx<T> coef[GTY * RS];
+  // two plane buffers, used alternately: one barrier per plane separates the
+  // writes of a buffer from the reads of the plane before the last
+  __shared__ __align__(16) cx<T> pls[2][PL];
+  __shared__ __align__(16) cx<T> coefs[2][GTY * RS];
   __shared__ double sh[GT / 64];
   const int t = threadIdx.x, c = t % PP, q = t / PP, w = t >> 6;
+  int it = 0;  // planes walked by this block (buffer parity)
   const bool cok = c < p;
   const int tilesx = (nx + GTX - 1) / GTX, tilesy = (ny + GTY - 1) / GTY;
   const int64_t units = grid_units_pp<PP>(nx, ny, nz);
@@ -189,6 +192,9 @@ __global__ __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(8))) void k_
       const cx<T> nn = (in && cok && z + 2 < nz) ? Z[(int64_t)(r0 + sxy * (z + 2)) * ldz + c] : czero<T>();
       const cx<T> hn = (hok && z + 1 < z1) ? Z[(int64_t)(hr0 + sxy * (z + 1)) * ldz + c] : czero<T>();
       // plane z into LDS
+      cx<T>* pl = pls[it & 1];
+      cx<T>* coef = coefs[it & 1];
+      ++it;
       if (q < NH) pl[(hy * W + hx) * PP + c] = hcur;
       pl[(ly * W + lx) * PP + c] = cur;
       if (loader) coef[t] = cv;
@@ -213,7 +219,6 @@ __global__ __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(8))) void k_
         }
       }
       if (NORM) nrm += (double)cabs2(yv);
-      __syncthreads();  // LDS is free for the next plane
       prev = cur;
       cur = nxt;
       nxt = nn;
