@@ -141,7 +141,9 @@ static void ctx_geometry(Ctx& c, int64_t n, int p, hipStream_t s) {
   int PP = 1;
   while (PP < p) PP <<= 1;
   const int64_t ntiles = (n + (NT / PP) - 1) / (NT / PP);
-  const int gmax = std::max(8, env_int("BLK_GRID", 1024));
+  // row passes: the vector-unit kernels (p < 16) gain from more resident
+  // workgroups; the matrix-core ones (two waves per SIMD) do not
+  const int gmax = std::max(8, env_int("BLK_GRID", PP < 16 ? 2048 : 1024));
   c.G = (int)std::min<int64_t>(gmax, ntiles);
   if (c.G >= 64) c.G &= ~7;  // multiple of 8 for the XCD remap
   c.Gs = (int)std::min<int64_t>(std::max(8, env_int("BLK_GRID_SPMM", 4096)), ntiles);
