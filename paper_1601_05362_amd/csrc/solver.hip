@@ -218,6 +218,22 @@ static void apply_op(Ctx& c, const DevOp<T>& A, const cx<T>* Z, int ldz, const c
         LAUNCH_CHECK();
         return;
       }
+      if constexpr ((PP == 16 || PP == 8) && GRAM && STORE && !NORM) {
+        if (A.kind == BLK_OP_CSR && A.gnx > 0) {
+          // grid-stencil pattern, p <= 16 with the Gram: the 2.5D product, then
+          // the Gram Z^T Y (FP64 accumulation) as a pass over the stored Y --
+          // fused, its staging and registers cost more than the pass
+          const int64_t units = grid_units_pp<PP>(A.gnx, A.gny, A.gnz);
+          k_spmm_grid<T, PP, SUB, STORE, false><<<(unsigned)units, GT, 0, c.s>>>(
+              A.gnx, A.gny, A.gnz, A.rowptr, A.val, Z, ldz, C, ldc, Y, ldy, c.p, nullptr, 0, st, gate);
+          LAUNCH_CHECK();
+          c.nblk[role] = c.G;
+          k_gram<T, double, PP, G_UNCONJ, false><<<c.G, NT, 0, c.s>>>(c.n, c.p, Z, ldz, Y, ldy, part, E,
+                                                                      st, gate);
+          LAUNCH_CHECK();
+          return;
+        }
+      }
     }
     if (A.kind == BLK_OP_CSR) {
       // Without a reduction every tile of RPB rows is its own block, which
