@@ -70,6 +70,15 @@ __device__ inline void cfms(cx<T>& acc, cx<T> a, cx<T> b) {
   acc.im = fma(-a.re, b.im, acc.im);
   acc.im = fma(-a.im, b.re, acc.im);
 }
+// Streaming (nontemporal) store of a block entry: n x p blocks are written
+// once per pass and read again only by a later launch, so they need not
+// occupy L2, which then keeps the rows a pass still reads.
+template <typename T>
+__device__ inline void st_nt(cx<T>* dst, cx<T> v) {
+  __builtin_nontemporal_store(v.re, &dst->re);
+  __builtin_nontemporal_store(v.im, &dst->im);
+}
+
 template <typename T>
 __device__ inline T cabs2(cx<T> a) {
   return a.re * a.re + a.im * a.im;

@@ -191,7 +191,7 @@ __global__ __launch_bounds__(NT) void k_dense_fin(int64_t n, int p, const cx<T>*
       y.im += v.im;
     }
     if (SUB) y = csub(Cm[r * ldc + col], y);
-    if (STORE) Y[r * ldy + col] = y;
+    if (STORE) st_nt(&Y[r * ldy + col], y);
     if (NORM) nrm += (double)cabs2(y);
   }
   if (NORM) {

@@ -215,7 +215,9 @@ __global__ __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(8))) void k_
         if (h6) cfma(acc, v[s6], nxt);
         if (cok) {
           yv = SUB ? csub(Cm[(int64_t)(r0 + sxy * z) * ldc + c], acc) : acc;
-          if (STORE) Y[(int64_t)(r0 + sxy * z) * ldy + c] = yv;
+          // streaming store: Y is not read again here, and keeping it out
+          // of L2 leaves room for the Z rows neighbouring tiles still need
+          if (STORE) st_nt(&Y[(int64_t)(r0 + sxy * z) * ldy + c], yv);
         }
       }
       if (NORM) nrm += (double)cabs2(yv);
@@ -323,7 +325,7 @@ __global__ __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(8))) void k_
         if (h6) cfma(acc, v[s6], nxt);
         if (cok) {
           yv = SUB ? csub(Cm[r * ldc + c], acc) : acc;
-          if (STORE) Y[r * ldy + c] = yv;
+          if (STORE) st_nt(&Y[r * ldy + c], yv);
         }
       }
       if (NORM) nrm += (double)cabs2(yv);

@@ -187,7 +187,7 @@ __global__ __launch_bounds__(NT) void k_axpy(int64_t n, int p, const cx<T>* Ain,
     __syncthreads();
     a = rowmul_sub<T, PP>(&bs[lr * PP], cs, c, a);
     if (ok)
-      Out[row * ldo + c] = a;
+      st_nt(&Out[row * ldo + c], a);
     else
       a = czero<T>();
     if (NORM) nrm += (double)cabs2(a);
@@ -267,7 +267,7 @@ __global__ __launch_bounds__(NT) void k_cholqr_pass3(int64_t n, int p, const cx<
     __syncthreads();
     cx<T> q = rowmul<T, PP>(&ws[lr * PP], cs, c, czero<T>());
     if (ok)
-      Q[row * ldq + c] = q;
+      st_nt(&Q[row * ldq + c], q);
     else
       q = czero<T>();
     if (GRAM) {
@@ -323,9 +323,9 @@ __global__ __launch_bounds__(NT) void k_update(int64_t n, int p, cx<T>* X, int l
     q = rowmul<T, PP>(&ss[lr * PP], cs2, c, q);
     if (WITH_U) v = rowmul<T, PP>(&us[lr * PP], cs2, c, v);
     if (ok) {
-      X[row * ldx + c] = x;
-      S[row * lds + c] = q;
-      if (WITH_U) U[row * ldu + c] = v;
+      st_nt(&X[row * ldx + c], x);
+      st_nt(&S[row * lds + c], q);
+      if (WITH_U) st_nt(&U[row * ldu + c], v);
     } else {
       v = czero<T>();
     }

@@ -124,7 +124,7 @@ __device__ inline void mf_store_D(z64* X, int ld, int64_t r0, int64_t n, int p, 
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int64_t row = r0 + 4 * v + (l >> 4);
-      if (row < n && col < p) X[row * ld + col] = z64{xr[jb][v], xi[jb][v]};
+      if (row < n && col < p) st_nt(&X[row * ld + col], z64{xr[jb][v], xi[jb][v]});
     }
   }
 }

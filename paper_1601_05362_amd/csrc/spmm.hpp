@@ -92,7 +92,7 @@ __global__ __launch_bounds__(NT) void k_spmm(int64_t n, const int32_t* __restric
         y = acc;
       }
       if (!cok) y = czero<T>();
-      if (STORE && cok) Y[row * ldy + c] = y;
+      if (STORE && cok) st_nt(&Y[row * ldy + c], y);
       if (GRAM && cok) zr = Z[row * ldz + c];
     }
     if (NORM) nrm += (double)cabs2(y);
@@ -192,7 +192,7 @@ __global__ __launch_bounds__(NT) void k_dense(int64_t n, const cx<T>* __restrict
     cx<T> y = czero<T>(), zr = czero<T>();
     if (row < n && cok) {
       y = SUB ? csub(Cm[row * ldc + c], acc) : acc;
-      if (STORE) Y[row * ldy + c] = y;
+      if (STORE) st_nt(&Y[row * ldy + c], y);
       if (GRAM) zr = Z[row * ldz + c];
     }
     if (NORM) nrm += (double)cabs2(y);
