@@ -88,7 +88,14 @@ __device__ inline void mf_load_D(const z64* X, int ld, int64_t r0, int64_t n, in
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int64_t row = r0 + 4 * v + (l >> 4);
-      z64 x = (row < n && col < p) ? X[row * ld + col] : czero<double>();
+      // streaming load: each D-layout instruction reads whole lines that no
+      // other load of the pass touches (A-layout reads of a row share lines
+      // between consecutive k-steps and stay cached)
+      z64 x = czero<double>();
+      if (row < n && col < p) {
+        x.re = __builtin_nontemporal_load(&X[row * ld + col].re);
+        x.im = __builtin_nontemporal_load(&X[row * ld + col].im);
+      }
       xr[jb][v] = x.re;
       xi[jb][v] = x.im;
     }
