@@ -244,7 +244,7 @@ static void apply_op(Ctx& c, const DevOp<T>& A, const cx<T>* Z, int ldz, const c
       if (GRAM || NORM) c.nblk[role] = c.Gs;
       // one tile per block: natural block order (consecutive tiles on
       // different XCDs); bounded grids: one contiguous slab per XCD
-      const int remap = (GRAM || NORM) ? 1 : env_int("BLK_SPMM_REMAP", 0);
+      const int remap = (GRAM || NORM) ? 1 : 0;
       k_spmm<T, PP, SUB, STORE, GRAM, NORM><<<(unsigned)G, NT, 0, c.s>>>(
           c.n, A.rowptr, A.colind, A.val, Z, ldz, C, ldc, Y, ldy, c.p, part, E, st, gate, remap);
     } else {
