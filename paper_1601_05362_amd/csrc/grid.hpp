@@ -6,8 +6,10 @@
 // read, since the pattern has been verified (k_grid_check).
 //
 // 2.5D blocking: a workgroup owns a GTX x GTY tile of an x-y plane and walks
-// GLZ consecutive planes (several tile columns per workgroup when the grid is
-// bounded by the reduction partials).  Each of its 32 thread rows owns one grid point and
+// zc consecutive planes (several tile columns per workgroup when the grid is
+// bounded by the reduction partials).  The host picks zc so that the
+// (tile, z chunk) units about fill the resident workgroup slots once: longer
+// chunks re-read fewer boundary planes, too few units leave CUs idle.  Each of its 32 thread rows owns one grid point and
 // p = 32 lanes its columns.  The current plane plus a one-point halo sits in
 // LDS (the +-x, +-y neighbours); the -z and +z neighbours stay in registers
 // as the walk advances, so each Z row is fetched about once per plane
@@ -21,13 +23,9 @@
 namespace blk {
 
 constexpr int GT = 1024;  // threads: 32 grid points x 32 columns
-constexpr int GTX = 8, GTY = 4, GLZ = 32;
+constexpr int GTX = 8, GTY = 4;
+constexpr int GRID_WG_PER_CU = 2;  // resident 1024-thread workgroups per CU
 static_assert(GTX * GTY * 32 == GT, "one thread row per tile point");
-
-// Grid units of a launch: (x-y tile, z chunk) pairs.
-__host__ __device__ inline int64_t grid_units(int nx, int ny, int nz) {
-  return (int64_t)((nx + GTX - 1) / GTX) * ((ny + GTY - 1) / GTY) * ((nz + GLZ - 1) / GLZ);
-}
 
 // x-y tile of the pipelined product for PP lanes per grid point: GT / PP
 // points, as square as the width 2..32 points per x-run allows.
@@ -47,9 +45,26 @@ struct GridTile<8> {
 };
 
 template <int PP>
-__host__ __device__ inline int64_t grid_units_pp(int nx, int ny, int nz) {
+__host__ __device__ inline int64_t grid_tiles_pp(int nx, int ny) {
   constexpr int TX = GridTile<PP>::X, TY = GridTile<PP>::Y;
-  return (int64_t)((nx + TX - 1) / TX) * ((ny + TY - 1) / TY) * ((nz + GLZ - 1) / GLZ);
+  return (int64_t)((nx + TX - 1) / TX) * ((ny + TY - 1) / TY);
+}
+
+// Units of a launch: (x-y tile, z chunk of zc planes) pairs.
+template <int PP>
+__host__ __device__ inline int64_t grid_units_pp(int nx, int ny, int nz, int zc) {
+  return grid_tiles_pp<PP>(nx, ny) * ((nz + zc - 1) / zc);
+}
+
+// Chunk length: the fewest chunks per tile column that give every resident
+// workgroup slot a unit.  At 128^3 (two slots on each of 256 CUs): 128
+// planes for p = 32 (512 tiles), 64 for p = 16, 32 for p = 8.
+template <int PP>
+inline int grid_zchunk(int nx, int ny, int nz, int slots) {
+  const int64_t tiles = grid_tiles_pp<PP>(nx, ny);
+  const int64_t chunks = (slots + tiles - 1) / tiles;
+  const int64_t zc = (nz + chunks - 1) / chunks;
+  return (int)(zc < 1 ? 1 : zc);
 }
 
 // Verify the stencil pattern: any mismatching row stores 1 to *bad.
@@ -106,7 +121,8 @@ template <typename T, int PP, bool SUB, bool STORE, bool NORM>
 __global__ __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(8))) void k_spmm_grid(
     int nx, int ny, int nz, const int32_t* __restrict__ rowptr, const cx<T>* __restrict__ val,
     const cx<T>* __restrict__ Z, int ldz, const cx<T>* __restrict__ Cm, int ldc,
-    cx<T>* __restrict__ Y, int ldy, int p, double* part, int E, const DevState* st, int gate) {
+    cx<T>* __restrict__ Y, int ldy, int p, int zc, double* part, int E, const DevState* st,
+    int gate) {
   if (st && gate >= st->stop_iter) return;
   constexpr int GTX = GridTile<PP>::X, GTY = GridTile<PP>::Y;
   static_assert(GTX * GTY * PP == GT, "one thread row per tile point");
@@ -124,7 +140,7 @@ __global__ __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(8))) void k_
   int it = 0;  // planes walked by this block (buffer parity)
   const bool cok = c < p;
   const int tilesx = (nx + GTX - 1) / GTX, tilesy = (ny + GTY - 1) / GTY;
-  const int64_t units = grid_units_pp<PP>(nx, ny, nz);
+  const int64_t units = grid_units_pp<PP>(nx, ny, nz, zc);
   const int sxy = nx * ny;  // rows fit int32 (n < 2^31 is checked by the caller)
   // halo point owned by thread row q (q < NH): ring of the (W x H) frame
   int hx = 0, hy = 0;
@@ -148,7 +164,7 @@ __global__ __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(8))) void k_
     const int bx = (int)(u % tilesx), by = (int)((u / tilesx) % tilesy);
     const int bz = (int)(u / ((int64_t)tilesx * tilesy));
     const int x = bx * GTX + q % GTX, y = by * GTY + q / GTX;
-    const int z0 = bz * GLZ, z1 = min(nz, z0 + GLZ);
+    const int z0 = bz * zc, z1 = min(nz, z0 + zc);
     const bool in = x < nx && y < ny;
     const int r0 = in ? x + nx * y : 0;
     const int ors = in ? bx * GTX + nx * y : 0;  // start of this point's run
@@ -254,8 +270,8 @@ __global__ __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(8))) void k_
                                                   const cx<T>* __restrict__ val,
                                                   const cx<T>* __restrict__ Z, int ldz,
                                                   const cx<T>* __restrict__ Cm, int ldc,
-                                                  cx<T>* __restrict__ Y, int ldy, int p, double* part,
-                                                  int E, const DevState* st, int gate) {
+                                                  cx<T>* __restrict__ Y, int ldy, int p, int zc,
+                                                  double* part, int E, const DevState* st, int gate) {
   if (st && gate >= st->stop_iter) return;
   constexpr int W = GTX + 2, H = GTY + 2, NH = 2 * (GTX + GTY);
   constexpr int PL = W * H * 32;  // plane + halo, in cx<T>
@@ -271,7 +287,7 @@ __global__ __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(8))) void k_
   const int c = threadIdx.x & 31, q = threadIdx.x >> 5, w = threadIdx.x >> 6;
   const bool cok = c < p;
   const int tilesx = (nx + GTX - 1) / GTX, tilesy = (ny + GTY - 1) / GTY;
-  const int64_t units = grid_units(nx, ny, nz);
+  const int64_t units = grid_units_pp<32>(nx, ny, nz, zc);
   const int64_t sxy = (int64_t)nx * ny;
   // halo point owned by thread row q (q < NH): ring of the (W x H) frame
   int hx = 0, hy = 0;
@@ -294,7 +310,7 @@ __global__ __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(8))) void k_
   for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
     const int bx = (int)(u % tilesx), by = (int)((u / tilesx) % tilesy), bz = (int)(u / ((int64_t)tilesx * tilesy));
     const int x = bx * GTX + q % GTX, y = by * GTY + q / GTX;
-    const int z0 = bz * GLZ, z1 = min(nz, z0 + GLZ);
+    const int z0 = bz * zc, z1 = min(nz, z0 + zc);
     const bool in = x < nx && y < ny;
     const int64_t r0 = in ? x + (int64_t)nx * y : 0;
     const int ex = bx * GTX + hx - 1, ey = by * GTY + hy - 1;

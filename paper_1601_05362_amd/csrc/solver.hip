@@ -122,6 +122,7 @@ struct Ctx {
   int G = 1;     // blocks of a row pass
   int Gs = 1;    // blocks of an operator application that reduces a Gram or norm
   int S = 0;     // first-stage reduction segments (0: p x p kernels read the partials)
+  int cus = 256; // compute units of the current device
   int Emax = 0;  // doubles per block partial
   int nblk[RO_COUNT] = {};  // blocks that wrote the partials of each role
   double* part[RO_COUNT] = {};
@@ -133,9 +134,19 @@ struct Ctx {
   z64* dws = nullptr;      // split-K partials of the dense product (DSPLIT x n x 32)
 };
 
+// Compute units of the current device (256 if the query fails).
+static int device_cus() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v < 1)
+    return 256;
+  return v;
+}
+
 // Launch geometry of a row pass over n rows of p columns.
 static void ctx_geometry(Ctx& c, int64_t n, int p, hipStream_t s) {
   c.s = s;
+  c.cus = device_cus();
   c.n = n;
   c.p = p;
   int PP = 1;
@@ -202,18 +213,20 @@ static void apply_op(Ctx& c, const DevOp<T>& A, const cx<T>* Z, int ldz, const c
         // grid-stencil pattern: 2.5D blocked product; with a reduction the
         // grid is bounded by the partial buffers (blocks loop over units)
         const int cap = std::max(c.G, c.Gs);
+        const int zc = grid_zchunk<PP>(A.gnx, A.gny, A.gnz, GRID_WG_PER_CU * c.cus);
+        const int64_t units = grid_units_pp<PP>(A.gnx, A.gny, A.gnz, zc);
         if constexpr (GRAM) {
-          const int64_t units = grid_units(A.gnx, A.gny, A.gnz);
           const int64_t G = std::min<int64_t>(units, cap);
           c.nblk[role] = (int)G;
           k_spmm_grid_walk<T, SUB, STORE, GRAM, NORM><<<(unsigned)G, GT, 0, c.s>>>(
-              A.gnx, A.gny, A.gnz, A.rowptr, A.val, Z, ldz, C, ldc, Y, ldy, c.p, part, E, st, gate);
+              A.gnx, A.gny, A.gnz, A.rowptr, A.val, Z, ldz, C, ldc, Y, ldy, c.p, zc, part, E, st,
+              gate);
         } else {
-          const int64_t units = grid_units_pp<PP>(A.gnx, A.gny, A.gnz);
           const int64_t G = NORM ? std::min<int64_t>(units, cap) : units;
           if (NORM) c.nblk[role] = (int)G;
           k_spmm_grid<T, PP, SUB, STORE, NORM><<<(unsigned)G, GT, 0, c.s>>>(
-              A.gnx, A.gny, A.gnz, A.rowptr, A.val, Z, ldz, C, ldc, Y, ldy, c.p, part, E, st, gate);
+              A.gnx, A.gny, A.gnz, A.rowptr, A.val, Z, ldz, C, ldc, Y, ldy, c.p, zc, part, E, st,
+              gate);
         }
         LAUNCH_CHECK();
         return;
@@ -223,9 +236,11 @@ static void apply_op(Ctx& c, const DevOp<T>& A, const cx<T>* Z, int ldz, const c
           // grid-stencil pattern, p <= 16 with the Gram: the 2.5D product, then
           // the Gram Z^T Y (FP64 accumulation) as a pass over the stored Y --
           // fused, its staging and registers cost more than the pass
-          const int64_t units = grid_units_pp<PP>(A.gnx, A.gny, A.gnz);
+          const int zc = grid_zchunk<PP>(A.gnx, A.gny, A.gnz, GRID_WG_PER_CU * c.cus);
+          const int64_t units = grid_units_pp<PP>(A.gnx, A.gny, A.gnz, zc);
           k_spmm_grid<T, PP, SUB, STORE, false><<<(unsigned)units, GT, 0, c.s>>>(
-              A.gnx, A.gny, A.gnz, A.rowptr, A.val, Z, ldz, C, ldc, Y, ldy, c.p, nullptr, 0, st, gate);
+              A.gnx, A.gny, A.gnz, A.rowptr, A.val, Z, ldz, C, ldc, Y, ldy, c.p, zc, nullptr, 0, st,
+              gate);
           LAUNCH_CHECK();
           c.nblk[role] = c.G;
           k_gram<T, double, PP, G_UNCONJ, false><<<c.G, NT, 0, c.s>>>(c.n, c.p, Z, ldz, Y, ldy, part, E,

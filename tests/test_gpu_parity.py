@@ -458,7 +458,10 @@ def test_refine_restarts(pkg, cfg1, method):
 # Grid-stencil operators: pattern analysis and the 2.5D blocked product
 # ---------------------------------------------------------------------------
 
-GRID_SHAPES = [(13, 11, 9), (8, 4, 70), (37, 29, 1), (16, 16, 33)]
+# Small grids walk one plane per unit (few x-y tiles: many z chunks fill the
+# CUs); 64 x 64 x 47 walks multi-plane chunks with a shorter last one (12,
+# 6 and 3 planes at p = 32, 16 and 8 on a 256-CU device).
+GRID_SHAPES = [(13, 11, 9), (8, 4, 70), (37, 29, 1), (16, 16, 33), (64, 64, 47)]
 
 
 @pytest.mark.parametrize("dims", GRID_SHAPES)
@@ -537,6 +540,27 @@ def test_grid_and_general_paths_agree(pkg, dev):
     assert np.max(np.abs(r1.hist[:k] - r2.hist[:k]) / r1.hist[:k]) < 1e-9
     assert max(r1.true_relres, r2.true_relres) < 1.5e-8
     assert _relerr(r2.X.cpu().numpy(), r1.X.cpu().numpy()) < 1e-5
+
+
+def test_grid_multiplane_chunks_solver(pkg, dev):
+    """A 64^3 grid, where the fused product-and-Gram walks chunks of 16
+    planes (on a 256-CU device): block COCR_rq through it tracks the run
+    through the general CSR kernel.  The two products sum in different
+    orders and the recurrences amplify the difference (1e-15 at the first
+    iteration, ~1e-9 by the 17th on this operator), so the history is held
+    to 1e-9 over 12 iterations and the iterate after 20 by its residual."""
+    A = W.helmholtz3d(64, 5.0, 0.02)
+    B = torch.as_tensor(W.cgauss(A.n, 32, seed=11), device=dev)
+    gen = pkg.CsrOperator.from_arrays(A.rowptr, A.colind, A.val, device=dev)
+    gen.structure = pkg._capi.BLK_STRUCT_GENERAL
+    grd = pkg.CsrOperator.from_arrays(A.rowptr, A.colind, A.val, device=dev).analyze()
+    assert grd.grid == (64, 64, 64)
+    r1 = pkg.blk_cocr_solve(gen, B, tol=1e-30, maxit=20)
+    r2 = pkg.blk_cocr_solve(grd, B, tol=1e-30, maxit=20)
+    assert r1.iters == r2.iters == 20
+    assert np.max(np.abs(r1.hist[:13] - r2.hist[:13]) / r1.hist[:13]) < 1e-9
+    assert abs(r1.true_relres - r2.true_relres) < 1e-6 * r1.true_relres
+    assert _relerr(r2.X.cpu().numpy(), r1.X.cpu().numpy()) < 1e-6
 
 
 def test_grid_mixed_precision(pkg, dev):
