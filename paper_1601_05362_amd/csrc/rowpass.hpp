@@ -166,8 +166,8 @@ __global__ __launch_bounds__(NT) void k_axpy(int64_t n, int p, const cx<T>* Ain,
   if (gate >= st->stop_iter) return;
   constexpr int RPB = NT / PP;
   __shared__ cx<T> cs[PP * PP];
-  __shared__ cx<T> bs[NT];
-  __shared__ cx<T> os[GM != G_NONE ? NT : 1];
+  __shared__ cx<T> bs[2 * NT];
+  __shared__ cx<T> os[GM != G_NONE ? 2 * NT : 1];
   __shared__ double sh[NT / 64];
   load_coef<T, PP>(cs, C, p);
   GramAcc<T, A, PP, GM == G_CONJ> g;
@@ -177,24 +177,38 @@ __global__ __launch_bounds__(NT) void k_axpy(int64_t n, int p, const cx<T>* Ain,
   const bool cok = c < p;
   int64_t t0, t1;
   tile_range((n + RPB - 1) / RPB, t0, t1);
-  for (int64_t t = t0; t < t1; ++t) {
-    const int64_t row = t * RPB + lr;
-    const bool ok = cok && row < n;
-    cx<T> a = ok ? Ain[row * lda + c] : czero<T>();
-    const cx<T> b = ok ? Bin[row * ldb + c] : czero<T>();
+  // two tiles per step: twice the loads in flight per barrier
+  for (int64_t t = t0; t < t1; t += 2) {
+    const int64_t row0 = t * RPB + lr, row1 = row0 + RPB;
+    const bool ok0 = cok && row0 < n, ok1 = cok && t + 1 < t1 && row1 < n;
+    cx<T> a0 = ok0 ? Ain[row0 * lda + c] : czero<T>();
+    cx<T> a1 = ok1 ? Ain[row1 * lda + c] : czero<T>();
+    const cx<T> b0 = ok0 ? Bin[row0 * ldb + c] : czero<T>();
+    const cx<T> b1 = ok1 ? Bin[row1 * ldb + c] : czero<T>();
     __syncthreads();
-    bs[threadIdx.x] = b;
+    bs[threadIdx.x] = b0;
+    bs[NT + threadIdx.x] = b1;
     __syncthreads();
-    a = rowmul_sub<T, PP>(&bs[lr * PP], cs, c, a);
-    if (ok)
-      st_nt(&Out[row * ldo + c], a);
+    a0 = rowmul_sub<T, PP>(&bs[lr * PP], cs, c, a0);
+    a1 = rowmul_sub<T, PP>(&bs[NT + lr * PP], cs, c, a1);
+    if (ok0)
+      st_nt(&Out[row0 * ldo + c], a0);
     else
-      a = czero<T>();
-    if (NORM) nrm += (double)cabs2(a);
+      a0 = czero<T>();
+    if (ok1)
+      st_nt(&Out[row1 * ldo + c], a1);
+    else
+      a1 = czero<T>();
+    if (NORM) {
+      nrm += (double)cabs2(a0);
+      nrm += (double)cabs2(a1);
+    }
     if (GM != G_NONE) {
-      os[threadIdx.x] = a;
+      os[threadIdx.x] = a0;
+      os[NT + threadIdx.x] = a1;
       __syncthreads();
       g.add(os, os);
+      g.add(os + NT, os + NT);
     }
   }
   double* dst = part + (size_t)blockIdx.x * E;
@@ -214,8 +228,8 @@ __global__ __launch_bounds__(NT) void k_cholqr_pass2(int64_t n, int p, const cx<
   if (gate >= st->stop_iter) return;
   constexpr int RPB = NT / PP;
   __shared__ cx<T> cs[PP * PP];
-  __shared__ cx<T> ws[NT];
-  __shared__ cx<T> os[NT];
+  __shared__ cx<T> ws[2 * NT];
+  __shared__ cx<T> os[2 * NT];
   load_coef<T, PP>(cs, M, p);
   GramAcc<T, double, PP, true> g;
   g.zero();
@@ -223,18 +237,25 @@ __global__ __launch_bounds__(NT) void k_cholqr_pass2(int64_t n, int p, const cx<
   const bool cok = c < p;
   int64_t t0, t1;
   tile_range((n + RPB - 1) / RPB, t0, t1);
-  for (int64_t t = t0; t < t1; ++t) {
-    const int64_t row = t * RPB + lr;
-    const bool ok = cok && row < n;
-    const cx<T> w = ok ? Win[row * ldw + c] : czero<T>();
+  // two tiles per step: twice the loads in flight per barrier
+  for (int64_t t = t0; t < t1; t += 2) {
+    const int64_t row0 = t * RPB + lr, row1 = row0 + RPB;
+    const bool ok0 = cok && row0 < n, ok1 = cok && t + 1 < t1 && row1 < n;
+    const cx<T> w0 = ok0 ? Win[row0 * ldw + c] : czero<T>();
+    const cx<T> w1 = ok1 ? Win[row1 * ldw + c] : czero<T>();
     __syncthreads();
-    ws[threadIdx.x] = w;
+    ws[threadIdx.x] = w0;
+    ws[NT + threadIdx.x] = w1;
     __syncthreads();
-    cx<T> y = rowmul<T, PP>(&ws[lr * PP], cs, c, czero<T>());
-    if (!ok) y = czero<T>();
-    os[threadIdx.x] = y;
+    cx<T> y0 = rowmul<T, PP>(&ws[lr * PP], cs, c, czero<T>());
+    cx<T> y1 = rowmul<T, PP>(&ws[NT + lr * PP], cs, c, czero<T>());
+    if (!ok0) y0 = czero<T>();
+    if (!ok1) y1 = czero<T>();
+    os[threadIdx.x] = y0;
+    os[NT + threadIdx.x] = y1;
     __syncthreads();
     g.add(os, os);
+    g.add(os + NT, os + NT);
   }
   g.store(part + (size_t)blockIdx.x * E, p);
 }
