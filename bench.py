@@ -99,6 +99,20 @@ def time_spmm(pkg, torch, A, Z, reps: int, c64: bool) -> float:
     return e0.elapsed_time(e1) / 1e3 / reps
 
 
+def per_iteration(pkg, torch, fn, A, B, short: int, long: int) -> float:
+    """Seconds per iteration of an FP64 solve: (time of `long` iterations -
+    time of `short`) / (long - short), so set-up and the final residual drop
+    out.  The tolerance is unreachable, so every run does its full count."""
+    t = {}
+    for it in (short, long):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn(A, B, tol=1e-300, maxit=it)
+        torch.cuda.synchronize()
+        t[it] = time.perf_counter() - t0
+    return (t[long] - t[short]) / (long - short)
+
+
 def cpu_baseline(Acsr, B, fp64_iters: int, sample_iters: int):
     """The oracle (numpy/scipy FP64) on a bounded sample: start-up plus
     `sample_iters` iterations of block COCR with residual orthonormalization,
@@ -146,6 +160,8 @@ def main():
     ap.add_argument("--cpu-sample-iters", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-mixed", action="store_true")
+    ap.add_argument("--no-per-iter", action="store_true",
+                    help="skip the per-iteration timings of the p = 32, p = 8 and 2D cases")
     ap.add_argument("--dense", type=int, default=0, metavar="N",
                     help="also time the dense Green's-function product at n = N (p as above)")
     args = ap.parse_args()
@@ -277,6 +293,23 @@ def main():
     mixed_s = float(np.median([r["mixed"][0] for r in results])) if not args.skip_mixed else None
     rm = results[-1]["mixed"][1] if not args.skip_mixed else None
 
+    # --- time per FP64 iteration of every case (outside the timed region) -------
+    per_iter = {}
+    if not args.no_per_iter:
+        solvers = (("cocr_rq", pkg.blk_cocr_solve), ("cocg_rq", pkg.blk_cocg_solve))
+        for pq in sorted({p, 8}, reverse=True):
+            Bq = torch.as_tensor(W.config2_rhs(A.n, pq), device=dev)
+            for name, fn in solvers:
+                per_iter[f"{N}^3_p{pq}_{name}_ms"] = round(
+                    per_iteration(pkg, torch, fn, Ad, Bq, 10, 110) * 1e3, 4)
+            del Bq
+        A1, B1 = W.config1()
+        A1d = pkg.CsrOperator.from_arrays(A1.rowptr, A1.colind, A1.val, device=dev)
+        B1d = torch.as_tensor(B1, device=dev)
+        for name, fn in solvers:
+            per_iter[f"64^2_p4_{name}_us"] = round(per_iteration(pkg, torch, fn, A1d, B1d, 20, 420) * 1e6, 2)
+        log(f"[bench] per iteration: {per_iter}")
+
     line = {
         "metric": "time to 1e-10 rel. residual, mixed vs FP64, n=2.1M p=32; SpMM % HBM peak",
         "value": round(mixed_s if mixed_s is not None else fp64_s, 4),
@@ -327,6 +360,7 @@ def main():
         },
         "cpu_baseline": None,
         "dense_product": dense,
+        "fp64_per_iteration": per_iter or None,
     }
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
