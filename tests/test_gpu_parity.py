@@ -637,3 +637,23 @@ def test_dense_mfma_solver_parity(pkg, dev):
     ref, H, it_tol, x_tol = _oracle_with_spread("cocr_rq", A, B, tol=1e-8, maxit=500, runs=4)
     r = pkg.blk_cocr_solve(Ad, torch.as_tensor(B, device=dev), tol=1e-8, maxit=500)
     _check_parity(r, ref, H, it_tol, x_tol)
+
+
+def test_mixed_precision_dense_p32(pkg, dev):
+    """The mixed form on a dense Green's operator at p = 32, whose complex64
+    inner products run on the FP32 matrix cores: it reaches the tolerance in
+    the true FP64 residual (the driver falls back to FP64 when an inner run
+    diverges), and its X is the oracle's within the tolerance's reach."""
+    n, p = 1024, 32
+    k = 2 * math.pi * 1.5
+    A = W.greens_sphere(n, k)
+    B = W.plane_waves3d(W.fibonacci_sphere(n), k, p) + 1e-3 * W.cgauss(n, p, seed=13)
+    ref = O.bl_cocr_rq(A, B, tol=1e-12, maxit=1000)
+    Ad = pkg.DenseOperator(torch.as_tensor(A, device=dev))
+    r = pkg.blk_cocr_solve(Ad, torch.as_tensor(B, device=dev), tol=1e-8, maxit=1000, precision="mixed")
+    assert r.status == pkg.BLK_CONVERGED, r.status_name
+    assert r.true_relres <= 1e-8
+    assert O.true_relres(A, B, r.X.cpu().numpy()) <= 1.01e-8
+    err = _relerr(r.X.cpu().numpy(), ref.X)
+    print(f"mixed dense p=32: iters={r.iters} trr={r.true_relres:.2e} |X-X_oracle|/|X_oracle|={err:.2e}")
+    assert err < 1e-5
