@@ -48,17 +48,22 @@ TRAFFIC_PROFILE = "profiles/k_spmm_c128_p32_helmholtz3d_128.md"
 
 
 def source_hash(paths) -> str:
+    """Hash of the code (comments and whitespace removed) of the given files or
+    (file, begin marker, end marker) regions."""
     import hashlib
+    import re
 
     h = hashlib.sha256()
     for item in paths:
         rel, begin, end = item if isinstance(item, tuple) else (item, None, None)
-        with open(os.path.join(ROOT, rel), "rb") as f:
+        with open(os.path.join(ROOT, rel), encoding="utf-8") as f:
             data = f.read()
         if begin is not None:
-            i = data.index(begin.encode())
-            data = data[i:data.index(end.encode(), i)]
-        h.update(data)
+            i = data.index(begin)
+            data = data[i:data.index(end, i)]
+        data = re.sub(r"/\*.*?\*/", " ", data, flags=re.S)
+        data = re.sub(r"//[^\n]*", " ", data)
+        h.update(" ".join(data.split()).encode())
     return h.hexdigest()[:16]
 
 

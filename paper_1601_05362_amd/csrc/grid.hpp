@@ -5,16 +5,18 @@
 // are read from the CSR (any coefficients); the column indices are not
 // read, since the pattern has been verified (k_grid_check).
 //
-// 2.5D blocking: a workgroup owns a GTX x GTY tile of an x-y plane and walks
-// zc consecutive planes (several tile columns per workgroup when the grid is
-// bounded by the reduction partials).  The host picks zc so that the
-// (tile, z chunk) units about fill the resident workgroup slots once: longer
-// chunks re-read fewer boundary planes, too few units leave CUs idle.  Each of its 32 thread rows owns one grid point and
-// p = 32 lanes its columns.  The current plane plus a one-point halo sits in
-// LDS (the +-x, +-y neighbours); the -z and +z neighbours stay in registers
-// as the walk advances, so each Z row is fetched about once per plane
-// instead of once per stored entry.  The same fused epilogues as the CSR
-// kernel: Y = C - A Z, the Gram Z^T Y (FP64 matrix cores) and ||Y||_F^2.
+// 2.5D blocking: a workgroup owns an x-y tile of a plane (8 x 4 points at
+// p = 32) and walks zc consecutive planes (several tile columns per
+// workgroup when the grid is bounded by the reduction partials).  The host
+// picks zc so that the (tile, z chunk) units about fill the resident
+// workgroup slots once: longer chunks re-read fewer boundary planes, too few
+// units leave CUs idle.  Each thread row owns one grid point and PP lanes its
+// columns.  The current plane plus a one-point halo sits in LDS (the +-x,
+// +-y neighbours); the -z and +z neighbours stay in registers as the walk
+// advances, so each Z row is fetched about once per plane instead of once
+// per stored entry.  Epilogues: Y = C - A Z and ||Y||_F^2 (k_spmm_grid), and
+// the Gram Z^T Y on the FP64 matrix cores (k_spmm_grid_walk, p = 32).  Y is
+// written with streaming stores.
 #pragma once
 
 #include "common.hpp"
