@@ -79,6 +79,12 @@ __device__ inline void st_nt(cx<T>* dst, cx<T> v) {
   __builtin_nontemporal_store(v.im, &dst->im);
 }
 
+// Streaming (nontemporal) load of an entry read once per pass.
+template <typename T>
+__device__ inline cx<T> ld_nt(const cx<T>* src) {
+  return cx<T>{__builtin_nontemporal_load(&src->re), __builtin_nontemporal_load(&src->im)};
+}
+
 template <typename T>
 __device__ inline T cabs2(cx<T> a) {
   return a.re * a.re + a.im * a.im;

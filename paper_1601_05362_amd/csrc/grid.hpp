@@ -194,10 +194,10 @@ __global__ __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(8))) void k_
         lc1 = rowptr[lrs + sxy * (z0 + 1) + runlen] - lb1;
       }
     }
-    cx<T> cv = (lrun && le < lc0) ? val[lb0 + le] : czero<T>();
+    cx<T> cv = (lrun && le < lc0) ? ld_nt(&val[lb0 + le]) : czero<T>();
     for (int z = z0; z < z1; ++z) {
       // plane z+1's coefficients (their offsets arrived one plane ago)
-      const cx<T> cvn = (lrun && z + 1 < z1 && le < lc1) ? val[lb1 + le] : czero<T>();
+      const cx<T> cvn = (lrun && z + 1 < z1 && le < lc1) ? ld_nt(&val[lb1 + le]) : czero<T>();
       // plane z+2's offsets and interior rows, plane z+1's halo
       int off2 = 0, lb2 = 0, lc2 = 0;
       if (z + 2 < z1) {
